@@ -1,0 +1,227 @@
+/*
+ * lob.h -- C ABI of the MI355X (gfx950) batched limit-order-book matcher.
+ *
+ * Many independent limit order books are processed at once; inside a book every
+ * message is processed strictly in order (JAX-LOB, Frey et al. 2023, Section 4.3:
+ * message processing in a continuous double auction is serial, parallelism comes
+ * from running many books side by side).  One GPU wavefront owns one book while
+ * it runs.
+ *
+ * Conventions for every entry point:
+ *   - Buffers are DEVICE pointers (e.g. a torch tensor's data_ptr() on the context's
+ *     device) unless the name ends in _host.  They are owned by the caller and must
+ *     stay valid until the stream reaches the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls
+ *     enqueue work and return without waiting for the device unless stated.
+ *   - Argument errors are reported synchronously as a negative lob_status and no
+ *     work is enqueued; lob_last_error() then describes the error.  Conditions
+ *     that depend on the data (a full side, an unknown order id, a full trade log,
+ *     times going backwards) never fail a call: they are counted per book and
+ *     read with lob_read_status.
+ *   - A context is used by one host thread at a time.  A book id may appear at
+ *     most once in one call; calls on one stream are processed in order.
+ *   - Every field of every record is int32: prices in ticks, quantities in shares,
+ *     ids, and times split into whole seconds and nanoseconds (Section 4.2).
+ *
+ * Records:
+ *   message (8 x int32)  {type, side, price, qty, order_id, trader_id, time_s, time_ns}
+ *       The fields of the paper's message m = [T, S, Q, P, OID, TID, Ts, Tns]
+ *       (Section 4.2, eq. "message") with price stored before qty.  type: 1 limit,
+ *       2 cancel, 3 delete, 4 market; any other type is skipped (zero padding,
+ *       Section 5.1.1).  side: +1 bid (buy), -1 ask (sell); any other side is
+ *       skipped.  price is ignored for market orders.  Times must not decrease
+ *       within a book (equal times keep arrival order); a decrease is flagged.
+ *   trade (6 x int32)    {price, qty, passive_id, aggressive_id, time_s, time_ns}
+ *       The trade t_j of Section 4.1 (eq. "trade"): the standing order's price,
+ *       the traded quantity, both order ids (standing first) and the aggressor's
+ *       time.
+ *   L2 snapshot          int32 [2][levels][2] = {asks, bids} x level x {price, qty}
+ *       Distinct prices best first (asks ascending, bids descending) with the
+ *       summed quantity of the orders at that price; a missing level is (-1, 0).
+ *   book dump            int32 [2][dump_cap][6] = {asks, bids} x order x
+ *       {P, Q, OID, TID, Ts, Tns} (Section 4, eq. "features") in price-time
+ *       priority; unused rows are -1 (the paper's empty marker).
+ *
+ * Matching (Section 4.1 and 4.2): a limit order is matched against the opposite
+ * side while that side is non-empty, its remaining quantity is positive and the
+ * best standing price overlaps its own (inclusive); each match trades
+ * min(remaining, standing) at the standing price; the remainder rests as one new
+ * order, or is rejected and counted when its side already holds `capacity`
+ * orders.  A market order matches with price 0 (sell) or INT32_MAX (buy) and its
+ * remainder is dropped.  Cancel and delete subtract their quantity from the order
+ * with that id on the message's side (or, if there is none, from the best-priority
+ * initial order -- id <= -9000 -- at the message's price, Section 5.1.1) and remove
+ * it once its quantity is <= 0; a quantity <= 0 does nothing.  The best standing
+ * order is the lowest ask / highest bid, earliest arrival first (eq. "best_price").
+ */
+#ifndef LOB_H
+#define LOB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lob_status;
+#define LOB_OK 0
+#define LOB_EINVAL (-1)   /* bad argument                                        */
+#define LOB_ENOMEM (-2)   /* device or host allocation failed                    */
+#define LOB_EDEVICE (-3)  /* a HIP call failed (message in lob_last_error)       */
+#define LOB_ECAP (-6)     /* a size exceeds what the context was created for     */
+
+#define LOB_MAX_CAPACITY 4096 /* orders per side per book                        */
+#define LOB_MAX_LEVELS 64     /* L2 depth                                        */
+
+/* l2_mode of lob_process_messages */
+#define LOB_L2_NONE 0
+#define LOB_L2_PER_MESSAGE 1 /* l2_out row k = snapshot after message k of msgs   */
+#define LOB_L2_FINAL 2       /* l2_out row i = snapshot after listed book i's last */
+
+/* per-book status flags (lob_book_status.flags) */
+#define LOB_BOOK_SIDE_FULL 1    /* a limit remainder was rejected: side full     */
+#define LOB_BOOK_TIME_ORDER 2   /* a message's time was earlier than the last one */
+#define LOB_BOOK_TRADE_FULL 4   /* trades were dropped: the book's trade log full */
+#define LOB_BOOK_FILLS_FULL 8   /* agent fills were dropped: the fills buffer full */
+
+typedef struct {
+  int32_t n_books;                       /* books in the context, >= 1             */
+  const int32_t *capacity_host;          /* [n_books] orders per side, 1..4096      */
+  int32_t l2_levels;                     /* L2 depth, 1..64 (the paper uses 10)     */
+  int32_t device;                        /* HIP device ordinal                     */
+  const int64_t *trade_log_records_host; /* [n_books] trade-log room per book, or  */
+                                         /* NULL: trade_log_default for every book */
+  int64_t trade_log_default;             /* records per book when the array is NULL */
+  uint32_t flags;                        /* reserved, 0                            */
+} lob_config;
+
+/* Per-book counters since creation or the last lob_reset (lob_read_status). */
+typedef struct {
+  int64_t n_msgs;           /* messages handed to the book, of any type          */
+  int64_t n_trades;         /* trades generated (including any dropped from log)  */
+  int64_t limit_qty;        /* summed qty of limit messages with qty > 0          */
+  int64_t market_qty;       /* summed qty of market messages with qty > 0         */
+  int64_t traded_qty;       /* summed trade quantity                             */
+  int64_t cancelled_qty;    /* quantity removed by cancel / delete               */
+  int64_t market_discarded; /* unmatched remainder of market orders              */
+  int64_t rejected_qty;     /* limit remainder rejected by a full side           */
+  int64_t cancel_miss;      /* cancels / deletes that found no order             */
+  int32_t flags;            /* LOB_BOOK_*                                        */
+  int32_t n_live[2];        /* resting orders now: [0] asks, [1] bids            */
+  int32_t pad;
+  int64_t log_records;      /* trades waiting in the book's log                  */
+} lob_book_status;
+
+/* Execution plan (lob_set_plan); lob_autotune picks one by measurement. */
+typedef struct {
+  int32_t lds_slots;       /* orders per side kept in LDS, a multiple of 64 in
+                              64..4096; a book with a larger capacity keeps the
+                              orders past this many in HBM                      */
+  int32_t books_per_block; /* wavefronts (one book each) per workgroup, 1..16    */
+  int32_t persistent;      /* 0: one wavefront per listed book;
+                              1: persistent wavefronts take books from a device
+                              queue, longest message stream first              */
+  int32_t waves_per_cu;    /* persistent mode: wavefronts launched per compute
+                              unit, 0 = as many as LDS and registers allow      */
+  int32_t split_buckets;   /* persistent mode, 1: books whose capacity fits in
+                              lds_slots and books that do not run as two queues
+                              in two concurrent launches; the second keeps
+                              lds_slots_big orders per side in LDS              */
+  int32_t lds_slots_big;   /* LDS window of the second launch (>= lds_slots)     */
+  int32_t reserved[2];
+} lob_plan;
+
+typedef struct lob_ctx lob_ctx;
+
+/* Create a context on cfg->device: every book empty, every trade log empty.  All
+ * device memory the context uses is allocated here (books, trade logs, queues).
+ * Returns LOB_EINVAL (bad config), LOB_ENOMEM or LOB_EDEVICE; *out is NULL then. */
+lob_status lob_create(const lob_config *cfg, lob_ctx **out);
+
+/* Free the context and its device memory (waits for the device first). */
+void lob_destroy(lob_ctx *ctx);
+
+/* Text of the last error on this context (ctx == NULL: the last lob_create failure
+ * on this thread).  Valid until the next call on the same context / thread. */
+const char *lob_last_error(const lob_ctx *ctx);
+
+/* Number of books, largest capacity and L2 depth of a context. */
+lob_status lob_info(const lob_ctx *ctx, int32_t *n_books, int32_t *max_capacity,
+                    int32_t *l2_levels);
+
+/* Replace / read the execution plan.  Results never depend on the plan. */
+lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan);
+lob_status lob_get_plan(const lob_ctx *ctx, lob_plan *plan);
+
+/* Process message streams (Section 4.2, one message at a time per book).
+ *   book_ids [n_books]    books to process (NULL: books 0..n_books-1)
+ *   msgs     [..][8]      message records
+ *   msg_offsets [n+1]     listed book i processes msgs[msg_offsets[i] ..
+ *                         msg_offsets[i+1]) in order; offsets non-decreasing
+ *   l2_mode, l2_out       LOB_L2_NONE (l2_out unused); LOB_L2_PER_MESSAGE:
+ *                         l2_out[k] = snapshot after message k (k indexes msgs);
+ *                         LOB_L2_FINAL: l2_out[i] = snapshot of listed book i at
+ *                         the end; each snapshot is [2][levels][2]
+ * Trades are appended to each book's trade log (lob_read_trades drains it).
+ * The books' state stays on the device between calls. */
+lob_status lob_process_messages(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
+                                const int32_t *msgs, const int64_t *msg_offsets,
+                                int32_t l2_mode, int32_t *l2_out, void *stream);
+
+/* One environment step per listed book (Section 5.1.3): the W data messages of
+ * window[i] (zero padding skipped), then the A agent messages of actions[i]
+ * (type 0 = no order), then the book's L2 snapshot into l2_out[i] and the trades
+ * of this step in which either side carries trader id agent_tid into
+ * agent_fills[i][0..F) (trade records, in order); agent_fill_counts[i] receives
+ * their number (more than F: the rest are dropped and flagged).  The step's trades
+ * are not appended to the trade log.  Allocates nothing and never waits for the
+ * device, so a sequence of steps can be captured in a HIP graph.
+ *   window [n][W][8], actions [n][A][8] (A may be 0, actions NULL),
+ *   l2_out [n][2][levels][2], agent_fills [n][F][6] (F may be 0),
+ *   agent_fill_counts [n] (may be NULL when F == 0). */
+lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
+                    const int32_t *window, int32_t W, const int32_t *actions, int32_t A,
+                    int32_t agent_tid, int32_t *l2_out, int32_t *agent_fills, int32_t F,
+                    int32_t *agent_fill_counts, void *stream);
+
+/* Current L2 snapshot of each listed book into l2_out [n][2][levels][2]. */
+lob_status lob_read_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *l2_out,
+                       void *stream);
+
+/* Drain trade logs.  counts[i] = records waiting in listed book i's log;
+ * offsets[0..n] = exclusive prefix sum of counts (offsets[n] = total).  Book i's
+ * records are copied, oldest first, to out[offsets[i] ..) as 6-int32 records and
+ * its log is emptied -- but only if offsets[i+1] <= max_records; a book that does
+ * not fit is left as it is (compare offsets[n] with max_records and call again
+ * with more room).  counts and offsets are device int64 arrays. */
+lob_status lob_read_trades(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *out,
+                           int64_t max_records, int64_t *counts, int64_t *offsets,
+                           void *stream);
+
+/* Per-book counters and flags into out[n] (device memory). */
+lob_status lob_read_status(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
+                           lob_book_status *out, void *stream);
+
+/* Checkpoint / restore: a book dump [n][2][dump_cap][6] per listed book.
+ * lob_read_book writes each side in priority order (rows past the live orders, or
+ * past dump_cap, are -1 / cut off).  lob_write_book replaces each listed book's
+ * orders by the dump's rows, taken in the given order up to the first row with
+ * Q <= 0 or the book's capacity; the rows must be in priority order (as
+ * lob_read_book writes them).  Counters and trade logs are not touched. */
+lob_status lob_read_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *out,
+                         int32_t dump_cap, void *stream);
+lob_status lob_write_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
+                          const int32_t *in, int32_t dump_cap, void *stream);
+
+/* Empty the listed books, their trade logs and their counters. */
+lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, void *stream);
+
+/* Diagnostic: run the wavefront primitives the matcher is built on (prefix scan,
+ * ballot, lane masks) on one wavefront and write 192 int32 results to out
+ * (device): [0,64) inclusive prefix sums of (lane % 7 + 1), [64,128) number of
+ * lanes <= lane with lane % 3 == 0, [128,192) number of lanes below lane. */
+lob_status lob_selftest(int32_t device, int32_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

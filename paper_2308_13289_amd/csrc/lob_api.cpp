@@ -1,0 +1,499 @@
+// lob_api.cpp -- the C ABI of liblob (declared in include/lob.h): argument checks,
+// device memory of a context, choice of kernel form and launch geometry.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <hipcub/hipcub.hpp>
+#include <string>
+#include <vector>
+
+#include "lob.h"
+#include "lob_internal.h"
+
+namespace lob {
+hipError_t launch_process(const ProcArgs &a, bool spill, bool persistent, int blocks, hipStream_t s);
+hipError_t set_process_lds_limit(size_t bytes);
+hipError_t occupancy_persistent(bool spill, int threads, size_t lds, int *blocks_per_cu);
+hipError_t launch_reset(BookHdr *hdr, const int32_t *ids, int n, int n_total, hipStream_t s);
+hipError_t launch_status(const BookHdr *hdr, const int32_t *ids, int n, int n_total, void *out, hipStream_t s);
+hipError_t launch_read_l2(const BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
+                          int32_t *out, hipStream_t s);
+hipError_t launch_read_book(const BookHdr *hdr, const int2 *books, const int32_t *ids, int n, int n_total,
+                            int dump_cap, int32_t *out, hipStream_t s);
+hipError_t launch_write_book(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int dump_cap,
+                             const int32_t *in, hipStream_t s);
+hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *ids, int n, int n_total,
+                              int32_t *out, int64_t max_records, int64_t *counts, int64_t *offsets,
+                              hipStream_t s);
+hipError_t launch_queue_keys(const BookHdr *hdr, const int32_t *ids, int n, int n_total, const int64_t *offs,
+                             int w1, int W, int split, uint64_t *keys, int32_t *vals, hipStream_t s);
+hipError_t launch_queue_ranges(const uint64_t *keys_sorted, int n, int32_t *range, int32_t *queue,
+                               hipStream_t s);
+hipError_t launch_selftest(int32_t *out, hipStream_t s);
+}  // namespace lob
+
+static_assert(sizeof(lob_book_status) == 96, "lob_book_status layout");
+
+struct lob_ctx {
+  int device = 0;
+  int n_books = 0, L = 10, max_cap = 0;
+  std::vector<int32_t> caps;
+  lob::BookHdr *d_hdr = nullptr;
+  int2 *d_books = nullptr;
+  int32_t *d_log = nullptr;
+  lob_plan plan{};
+  std::string err;
+  int num_cus = 0;
+  size_t max_lds = 0;
+  // persistent-queue workspace
+  uint64_t *d_keys = nullptr, *d_keys_sorted = nullptr;
+  int32_t *d_vals = nullptr, *d_order = nullptr, *d_range = nullptr, *d_queue = nullptr;
+  void *d_sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+lob_status fail(lob_ctx *c, lob_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+lob_status hip_fail(lob_ctx *c, hipError_t e, const char *what) {
+  return fail(c, LOB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+void free_ctx(lob_ctx *c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->d_hdr);
+  (void)hipFree(c->d_books);
+  (void)hipFree(c->d_log);
+  (void)hipFree(c->d_keys);
+  (void)hipFree(c->d_keys_sorted);
+  (void)hipFree(c->d_vals);
+  (void)hipFree(c->d_order);
+  (void)hipFree(c->d_range);
+  (void)hipFree(c->d_queue);
+  (void)hipFree(c->d_sort_tmp);
+  if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  delete c;
+}
+
+lob_status check_list(lob_ctx *c, int32_t n) {
+  if (!c) return LOB_EINVAL;
+  if (n < 0 || n > c->n_books) return fail(c, LOB_EINVAL, "n_books out of range");
+  return LOB_OK;
+}
+
+// LDS words (int2) one wave needs for a window of W slots: 3 pair arrays per side,
+// plus L ints of L2 scratch.
+int lds_int2_per_wave(int W, int L) { return 6 * W + (L + 1) / 2; }
+
+struct Geometry {
+  int W;
+  bool spill;
+  int bpb;
+  int per_wave;
+};
+
+// Window and books-per-block for one launch over books of capacity <= cap_limit.
+lob_status geometry(lob_ctx *c, int window, int cap_limit, int bpb_want, Geometry *g) {
+  int W = std::min(window, cap_limit);
+  if (W < 1) W = 1;
+  int bpb = std::max(1, std::min(16, bpb_want));
+  int per_wave = lds_int2_per_wave(W, c->L);
+  while (bpb > 1 && (size_t)bpb * per_wave * sizeof(int2) > c->max_lds) --bpb;
+  if ((size_t)per_wave * sizeof(int2) > c->max_lds) return fail(c, LOB_ECAP, "LDS window does not fit");
+  g->W = W;
+  g->spill = cap_limit > W;
+  g->bpb = bpb;
+  g->per_wave = per_wave;
+  return LOB_OK;
+}
+
+lob_status run_process(lob_ctx *c, lob::ProcArgs a, hipStream_t s) {
+  if (a.n == 0) return LOB_OK;
+  const lob_plan &p = c->plan;
+  Geometry g;
+  lob_status st = geometry(c, p.lds_slots, c->max_cap, p.books_per_block, &g);
+  if (st != LOB_OK) return st;
+  a.W = g.W;
+  a.bpb = g.bpb;
+  a.lds_int2_per_wave = g.per_wave;
+  if (!p.persistent) {
+    hipError_t e = lob::launch_process(a, g.spill, false, 0, s);
+    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+  }
+  // persistent: queue of listed books, longest stream first, in one or two buckets
+  const bool split = p.split_buckets && c->max_cap > g.W;
+  hipError_t e = lob::launch_queue_keys(c->d_hdr, a.book_ids, a.n, c->n_books, a.offs, a.w1, g.W, split ? 1 : 0, c->d_keys,
+                                        c->d_vals, s);
+  if (e != hipSuccess) return hip_fail(c, e, "queue keys");
+  size_t tmp = c->sort_tmp_bytes;
+  e = hipcub::DeviceRadixSort::SortPairs(c->d_sort_tmp, tmp, c->d_keys, c->d_keys_sorted, c->d_vals, c->d_order,
+                                         a.n, 0, 64, s);
+  if (e != hipSuccess) return hip_fail(c, e, "queue sort");
+  e = lob::launch_queue_ranges(c->d_keys_sorted, a.n, c->d_range, c->d_queue, s);
+  if (e != hipSuccess) return hip_fail(c, e, "queue ranges");
+  a.queue = c->d_queue;
+  a.order = c->d_order;
+  a.bucket_range = c->d_range;
+
+  auto grid_for = [&](const Geometry &gg, int *blocks) -> lob_status {
+    int per_cu = 0;
+    hipError_t ee = lob::occupancy_persistent(gg.spill, gg.bpb * lob::kWave,
+                                              (size_t)gg.bpb * gg.per_wave * sizeof(int2), &per_cu);
+    if (ee != hipSuccess) return hip_fail(c, ee, "occupancy");
+    if (per_cu < 1) per_cu = 1;
+    if (p.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, p.waves_per_cu / gg.bpb));
+    *blocks = per_cu * c->num_cus;
+    return LOB_OK;
+  };
+
+  if (!split) {
+    a.bucket = 0;
+    int blocks = 0;
+    if ((st = grid_for(g, &blocks)) != LOB_OK) return st;
+    e = lob::launch_process(a, g.spill, true, blocks, s);
+    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "persistent launch");
+  }
+  // bucket 0: capacity <= W, fully LDS-resident; bucket 1: the rest, on a side
+  // stream with its own (larger) window, forked from and joined back into s
+  Geometry g0, g1;
+  if ((st = geometry(c, g.W, g.W, p.books_per_block, &g0)) != LOB_OK) return st;
+  const int big = std::max(p.lds_slots_big, g.W);
+  if ((st = geometry(c, big, c->max_cap, p.books_per_block, &g1)) != LOB_OK) return st;
+  int b0 = 0, b1 = 0;
+  if ((st = grid_for(g0, &b0)) != LOB_OK) return st;
+  if ((st = grid_for(g1, &b1)) != LOB_OK) return st;
+  if ((e = hipEventRecord(c->ev_fork, s)) != hipSuccess) return hip_fail(c, e, "fork");
+  if ((e = hipStreamWaitEvent(c->side_stream, c->ev_fork, 0)) != hipSuccess) return hip_fail(c, e, "fork");
+  lob::ProcArgs a1 = a;
+  a1.bucket = 1;
+  a1.W = g1.W;
+  a1.bpb = g1.bpb;
+  a1.lds_int2_per_wave = g1.per_wave;
+  e = lob::launch_process(a1, g1.spill, true, b1, c->side_stream);
+  if (e != hipSuccess) return hip_fail(c, e, "persistent launch (bucket 1)");
+  a.bucket = 0;
+  a.W = g0.W;
+  a.bpb = g0.bpb;
+  a.lds_int2_per_wave = g0.per_wave;
+  e = lob::launch_process(a, false, true, b0, s);
+  if (e != hipSuccess) return hip_fail(c, e, "persistent launch (bucket 0)");
+  if ((e = hipEventRecord(c->ev_join, c->side_stream)) != hipSuccess) return hip_fail(c, e, "join");
+  if ((e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess) return hip_fail(c, e, "join");
+  return LOB_OK;
+}
+
+lob::ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n) {
+  lob::ProcArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.hdr = c->d_hdr;
+  a.books = c->d_books;
+  a.log = c->d_log;
+  a.book_ids = ids;
+  a.n = n;
+  a.n_total = c->n_books;
+  a.levels = c->L;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
+  if (!out) return LOB_EINVAL;
+  *out = nullptr;
+  g_create_error.clear();
+  auto bad = [](const char *m) {
+    g_create_error = m;
+    return LOB_EINVAL;
+  };
+  if (!cfg) return bad("cfg is NULL");
+  if (cfg->n_books < 1) return bad("n_books < 1");
+  if (!cfg->capacity_host) return bad("capacity_host is NULL");
+  if (cfg->l2_levels < 1 || cfg->l2_levels > LOB_MAX_LEVELS) return bad("l2_levels out of range");
+  if (!cfg->trade_log_records_host && cfg->trade_log_default < 0) return bad("trade_log_default < 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+    return bad("no such HIP device");
+  lob_ctx *c = new lob_ctx();
+  c->device = cfg->device;
+  c->n_books = cfg->n_books;
+  c->L = cfg->l2_levels;
+  c->caps.assign(cfg->capacity_host, cfg->capacity_host + cfg->n_books);
+  std::vector<lob::BookHdr> hdr(cfg->n_books);
+  int64_t book_int2 = 0, log_rec = 0;
+  for (int i = 0; i < cfg->n_books; ++i) {
+    const int cap = c->caps[i];
+    if (cap < 1 || cap > LOB_MAX_CAPACITY) {
+      delete c;
+      return bad("capacity out of range");
+    }
+    const int64_t lc = cfg->trade_log_records_host ? cfg->trade_log_records_host[i] : cfg->trade_log_default;
+    if (lc < 0) {
+      delete c;
+      return bad("negative trade log size");
+    }
+    c->max_cap = std::max(c->max_cap, cap);
+    lob::BookHdr &h = hdr[i];
+    std::memset(&h, 0, sizeof(h));
+    h.cap = cap;
+    h.book_off = book_int2;
+    h.log_off = log_rec;
+    h.log_cap = lc;
+    book_int2 += 6LL * cap;
+    log_rec += lc;
+  }
+  DeviceGuard g(c->device);
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, c->device);
+  if (e != hipSuccess || !g.ok) {
+    g_create_error = "hipGetDeviceProperties failed";
+    delete c;
+    return LOB_EDEVICE;
+  }
+  c->num_cus = prop.multiProcessorCount;
+  c->max_lds = prop.sharedMemPerBlock;
+  if (prop.maxSharedMemoryPerMultiProcessor > 0)
+    c->max_lds = std::min<size_t>(c->max_lds, prop.maxSharedMemoryPerMultiProcessor);
+  if (c->max_lds == 0) c->max_lds = 65536;
+  auto alloc = [&](void **p, size_t bytes) {
+    return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess;
+  };
+  size_t sort_tmp = 0;
+  bool ok = alloc((void **)&c->d_hdr, sizeof(lob::BookHdr) * hdr.size()) &&
+            alloc((void **)&c->d_books, sizeof(int2) * (size_t)book_int2) &&
+            alloc((void **)&c->d_log, sizeof(int32_t) * lob::kTradeFields * (size_t)log_rec) &&
+            alloc((void **)&c->d_keys, sizeof(uint64_t) * c->n_books) &&
+            alloc((void **)&c->d_keys_sorted, sizeof(uint64_t) * c->n_books) &&
+            alloc((void **)&c->d_vals, sizeof(int32_t) * c->n_books) &&
+            alloc((void **)&c->d_order, sizeof(int32_t) * c->n_books) &&
+            alloc((void **)&c->d_range, sizeof(int32_t) * 4) && alloc((void **)&c->d_queue, sizeof(int32_t) * 4);
+  if (ok) {
+    ok = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, c->d_keys, c->d_keys_sorted, c->d_vals, c->d_order,
+                                            c->n_books, 0, 64) == hipSuccess &&
+         alloc(&c->d_sort_tmp, sort_tmp);
+    c->sort_tmp_bytes = std::max<size_t>(sort_tmp, 256);
+  }
+  if (!ok) {
+    g_create_error = "device allocation failed";
+    free_ctx(c);
+    return LOB_ENOMEM;
+  }
+  e = hipMemcpy(c->d_hdr, hdr.data(), sizeof(lob::BookHdr) * hdr.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) (void)lob::set_process_lds_limit(c->max_lds);  // advisory on this platform
+  if (e != hipSuccess) {
+    g_create_error = std::string("context setup: ") + hipGetErrorString(e);
+    free_ctx(c);
+    return LOB_EDEVICE;
+  }
+  // default plan: whole books in LDS when they fit comfortably, otherwise a
+  // 256-slot window with the rest in HBM; four books per workgroup
+  c->plan.lds_slots = c->max_cap <= 1024 ? c->max_cap : 256;
+  c->plan.books_per_block = 4;
+  c->plan.persistent = 0;
+  c->plan.waves_per_cu = 0;
+  c->plan.split_buckets = 0;
+  c->plan.lds_slots_big = c->max_cap;
+  *out = c;
+  return LOB_OK;
+}
+
+void lob_destroy(lob_ctx *ctx) { free_ctx(ctx); }
+
+const char *lob_last_error(const lob_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+lob_status lob_info(const lob_ctx *ctx, int32_t *n_books, int32_t *max_capacity, int32_t *l2_levels) {
+  if (!ctx) return LOB_EINVAL;
+  if (n_books) *n_books = ctx->n_books;
+  if (max_capacity) *max_capacity = ctx->max_cap;
+  if (l2_levels) *l2_levels = ctx->L;
+  return LOB_OK;
+}
+
+lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan) {
+  if (!ctx || !plan) return LOB_EINVAL;
+  if (plan->lds_slots < 1 || plan->lds_slots > LOB_MAX_CAPACITY) return fail(ctx, LOB_EINVAL, "lds_slots");
+  if (plan->books_per_block < 1 || plan->books_per_block > 16) return fail(ctx, LOB_EINVAL, "books_per_block");
+  if (plan->persistent != 0 && plan->persistent != 1) return fail(ctx, LOB_EINVAL, "persistent");
+  if (plan->waves_per_cu < 0) return fail(ctx, LOB_EINVAL, "waves_per_cu");
+  if (plan->split_buckets != 0 && plan->split_buckets != 1) return fail(ctx, LOB_EINVAL, "split_buckets");
+  if (plan->split_buckets && plan->lds_slots_big < plan->lds_slots)
+    return fail(ctx, LOB_EINVAL, "lds_slots_big < lds_slots");
+  const size_t need = (size_t)lds_int2_per_wave(std::min(plan->lds_slots, ctx->max_cap), ctx->L) * sizeof(int2);
+  if (need > ctx->max_lds) return fail(ctx, LOB_ECAP, "lds_slots does not fit in LDS");
+  if (plan->split_buckets &&
+      (size_t)lds_int2_per_wave(std::min(plan->lds_slots_big, ctx->max_cap), ctx->L) * sizeof(int2) > ctx->max_lds)
+    return fail(ctx, LOB_ECAP, "lds_slots_big does not fit in LDS");
+  ctx->plan = *plan;
+  return LOB_OK;
+}
+
+lob_status lob_get_plan(const lob_ctx *ctx, lob_plan *plan) {
+  if (!ctx || !plan) return LOB_EINVAL;
+  *plan = ctx->plan;
+  return LOB_OK;
+}
+
+lob_status lob_process_messages(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *msgs,
+                                const int64_t *msg_offsets, int32_t l2_mode, int32_t *l2_out, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (n_books == 0) return LOB_OK;
+  if (!msgs || !msg_offsets) return fail(ctx, LOB_EINVAL, "msgs / msg_offsets is NULL");
+  if (!aligned16(msgs)) return fail(ctx, LOB_EINVAL, "msgs must be 16-byte aligned");
+  if (l2_mode < LOB_L2_NONE || l2_mode > LOB_L2_FINAL) return fail(ctx, LOB_EINVAL, "l2_mode");
+  if (l2_mode != LOB_L2_NONE && !l2_out) return fail(ctx, LOB_EINVAL, "l2_out is NULL");
+  DeviceGuard g(ctx->device);
+  lob::ProcArgs a = base_args(ctx, book_ids, n_books);
+  a.msgs = msgs;
+  a.offs = msg_offsets;
+  a.l2_mode = l2_mode;
+  a.l2_out = l2_out;
+  return run_process(ctx, a, (hipStream_t)stream);
+}
+
+lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window, int32_t W,
+                    const int32_t *actions, int32_t A, int32_t agent_tid, int32_t *l2_out, int32_t *agent_fills,
+                    int32_t F, int32_t *agent_fill_counts, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (W < 0 || A < 0 || F < 0) return fail(ctx, LOB_EINVAL, "negative W / A / F");
+  if (n_books == 0) return LOB_OK;
+  if (W > 0 && (!window || !aligned16(window))) return fail(ctx, LOB_EINVAL, "window NULL or not 16-byte aligned");
+  if (A > 0 && (!actions || !aligned16(actions))) return fail(ctx, LOB_EINVAL, "actions NULL or not aligned");
+  if (!l2_out) return fail(ctx, LOB_EINVAL, "l2_out is NULL");
+  if (F > 0 && (!agent_fills || !agent_fill_counts)) return fail(ctx, LOB_EINVAL, "agent_fills is NULL");
+  DeviceGuard g(ctx->device);
+  lob::ProcArgs a = base_args(ctx, book_ids, n_books);
+  a.log = nullptr;
+  a.msgs = W > 0 ? window : nullptr;
+  a.w1 = W;
+  a.msgs2 = A > 0 ? actions : nullptr;
+  a.w2 = A;
+  a.l2_mode = LOB_L2_FINAL;
+  a.l2_out = l2_out;
+  a.fills = F > 0 ? agent_fills : nullptr;
+  a.fill_cap = F;
+  a.fill_counts = F > 0 ? agent_fill_counts : nullptr;
+  a.agent_tid = agent_tid;
+  // a step never uses the persistent queue (keeps it capturable and cheap)
+  lob_plan saved = ctx->plan;
+  ctx->plan.persistent = 0;
+  st = run_process(ctx, a, (hipStream_t)stream);
+  ctx->plan = saved;
+  return st;
+}
+
+lob_status lob_read_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *l2_out, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (n_books == 0) return LOB_OK;
+  if (!l2_out) return fail(ctx, LOB_EINVAL, "l2_out is NULL");
+  DeviceGuard g(ctx->device);
+  hipError_t e = lob::launch_read_l2(ctx->d_hdr, ctx->d_books, book_ids, n_books, ctx->n_books, ctx->L, l2_out,
+                                     (hipStream_t)stream);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "read_l2");
+}
+
+lob_status lob_read_trades(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *out,
+                           int64_t max_records, int64_t *counts, int64_t *offsets, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (max_records < 0) return fail(ctx, LOB_EINVAL, "max_records < 0");
+  if (!offsets || (n_books > 0 && !counts)) return fail(ctx, LOB_EINVAL, "counts / offsets is NULL");
+  if (max_records > 0 && !out) return fail(ctx, LOB_EINVAL, "out is NULL");
+  DeviceGuard g(ctx->device);
+  hipError_t e = lob::launch_read_trades(ctx->d_hdr, ctx->d_log, book_ids, n_books, ctx->n_books, out, max_records, counts,
+                                         offsets, (hipStream_t)stream);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "read_trades");
+}
+
+lob_status lob_read_status(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, lob_book_status *out,
+                           void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (n_books == 0) return LOB_OK;
+  if (!out) return fail(ctx, LOB_EINVAL, "out is NULL");
+  DeviceGuard g(ctx->device);
+  hipError_t e = lob::launch_status(ctx->d_hdr, book_ids, n_books, ctx->n_books, out, (hipStream_t)stream);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "read_status");
+}
+
+lob_status lob_read_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *out, int32_t dump_cap,
+                         void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (dump_cap < 1) return fail(ctx, LOB_EINVAL, "dump_cap < 1");
+  if (n_books == 0) return LOB_OK;
+  if (!out) return fail(ctx, LOB_EINVAL, "out is NULL");
+  DeviceGuard g(ctx->device);
+  hipError_t e = lob::launch_read_book(ctx->d_hdr, ctx->d_books, book_ids, n_books, ctx->n_books, dump_cap, out,
+                                       (hipStream_t)stream);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "read_book");
+}
+
+lob_status lob_write_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *in,
+                          int32_t dump_cap, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (dump_cap < 1) return fail(ctx, LOB_EINVAL, "dump_cap < 1");
+  if (n_books == 0) return LOB_OK;
+  if (!in) return fail(ctx, LOB_EINVAL, "in is NULL");
+  DeviceGuard g(ctx->device);
+  hipError_t e = lob::launch_write_book(ctx->d_hdr, ctx->d_books, book_ids, n_books, ctx->n_books, dump_cap, in,
+                                        (hipStream_t)stream);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "write_book");
+}
+
+lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (n_books == 0) return LOB_OK;
+  DeviceGuard g(ctx->device);
+  hipError_t e = lob::launch_reset(ctx->d_hdr, book_ids, n_books, ctx->n_books, (hipStream_t)stream);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "reset");
+}
+
+lob_status lob_selftest(int32_t device, int32_t *out, void *stream) {
+  if (!out) return LOB_EINVAL;
+  DeviceGuard g(device);
+  if (!g.ok) return LOB_EDEVICE;
+  return lob::launch_selftest(out, (hipStream_t)stream) == hipSuccess ? LOB_OK : LOB_EDEVICE;
+}
+
+}  // extern "C"

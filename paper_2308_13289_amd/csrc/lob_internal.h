@@ -1,0 +1,77 @@
+// lob_internal.h -- device-side layout shared by the kernels and the host code of liblob.
+//
+// Device memory of a context:
+//   hdr   [n_books] BookHdr           counters, live counts, where the book's arrays are
+//   books [sum 6*cap] int2            per book, per side s (0 asks, 1 bids), three pair
+//                                     arrays of `cap` entries each, kept in price-time
+//                                     priority (slot 0 = best):  (P, Q), (OID, TID),
+//                                     (Ts, Tns)  -- the six order features of the paper's
+//                                     Section 4, two per 8-byte word
+//   log   [sum log_cap][6] int32      per book, the trade records not yet read
+#pragma once
+#include <stdint.h>
+
+namespace lob {
+
+constexpr int kWave = 64;
+constexpr int kMsgFields = 8;
+constexpr int kTradeFields = 6;
+
+// flags (same values as LOB_BOOK_* in lob.h)
+constexpr int kFlagSideFull = 1;
+constexpr int kFlagTimeOrder = 2;
+constexpr int kFlagTradeFull = 4;
+constexpr int kFlagFillsFull = 8;
+constexpr int kFlagBadLoad = 16;
+
+struct alignas(16) BookHdr {
+  int32_t n[2];  // live orders: [0] asks, [1] bids
+  int32_t cap;   // capacity per side
+  int32_t flags;
+  int64_t book_off;   // first int2 of this book's arrays in `books`
+  int64_t log_off;    // first record of this book's trade log
+  int64_t log_cap;    // records the log can hold
+  int64_t log_count;  // records waiting in the log
+  int64_t n_msgs, n_trades, limit_qty, market_qty, traded_qty, cancelled_qty, market_discarded,
+      rejected_qty, cancel_miss;
+  int32_t last_ts, last_tns;  // time of the last processed message
+  int32_t seen_time;          // 1 once a message with a valid type was processed
+  int32_t pad[3];
+};
+static_assert(sizeof(BookHdr) == 144, "BookHdr layout");
+
+// Arguments of the matching kernels (passed by value).
+struct ProcArgs {
+  BookHdr *hdr;
+  int2 *books;
+  int32_t *log;        // trade log base, or nullptr: do not log trades
+  const int32_t *book_ids;  // nullptr: listed book i is book i
+  int32_t n;                // listed books
+  int32_t n_total;          // books in the context (ids outside [0, n_total) are skipped)
+  // message source 1: msgs[offs[i] .. offs[i+1]) or, when offs == nullptr, msgs[i*w1 .. (i+1)*w1)
+  const int32_t *msgs;
+  const int64_t *offs;
+  int32_t w1;
+  // message source 2 (step actions): msgs2[i*w2 .. (i+1)*w2)
+  const int32_t *msgs2;
+  int32_t w2;
+  int32_t l2_mode;     // 0 none, 1 per message (indexed like source 1), 2 final (per listed book)
+  int32_t levels;
+  int32_t *l2_out;
+  // agent fills (step form)
+  int32_t *fills;      // [n][fill_cap][6] or nullptr
+  int32_t fill_cap;
+  int32_t *fill_counts;
+  int32_t agent_tid;
+  // LDS window
+  int32_t W;           // LDS slots per side-pair array
+  int32_t bpb;         // books (waves) per block
+  int32_t lds_int2_per_wave;
+  // persistent mode
+  int32_t *queue;      // [2] counters (one per bucket queue) or nullptr
+  const int32_t *order;  // listed indices, longest stream first
+  const int32_t *bucket_range;  // device [3]: queue q covers order[range[q] .. range[q+1])
+  int32_t bucket;      // which queue this launch serves
+};
+
+}  // namespace lob

@@ -1,0 +1,844 @@
+// lob_kernels.hip -- gfx950 kernels of the batched limit-order-book matcher.
+//
+// One wavefront (64 lanes) owns one book for the whole of a call.  Each side of the
+// book is kept SORTED in price-time priority (slot 0 = best) as three arrays of
+// int2 pairs -- (P, Q), (OID, TID), (Ts, Tns) -- staged in LDS for the duration of
+// the call.  Slot s of a side sits on lane s % 64 of chunk s / 64, so every book
+// operation is a handful of wave-wide steps over the live chunks:
+//   best standing order      slot 0 of the opposite side
+//   matching loop            one inclusive prefix scan (DPP) of the crossing
+//                            quantities: the fills are a prefix of the side, all of
+//                            them full except possibly the last (Section 4.1)
+//   add                      ballot-count of the orders ahead, shift the rest up
+//   cancel / delete          ballot on OID (then on the initial-order rule of
+//                            Section 5.1.1), shift the rest down if it empties
+//   L2 top-k                 ballot of price changes + the same prefix scan
+// The paper keeps unsorted arrays because under vmap every branch runs for every
+// message and a sort would be paid each time (Section 4.3); here the eight
+// (type x side) cases are a wave-uniform scalar branch, so only the work of the
+// message at hand is done.
+//
+// Messages stream from HBM in 64-message chunks (one 32-byte record per lane) and
+// are broadcast to scalar registers one at a time.  Trades go straight to the
+// book's trade log as 24-byte records, one lane per fill, in fill order.
+//
+// Books whose capacity exceeds the LDS window W keep slots >= W in their HBM
+// arrays (SPILL = true); the head of each side stays in LDS.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include "lob_internal.h"
+
+namespace lob {
+namespace {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ int popc(uint64_t m) { return __builtin_popcountll(m); }
+__device__ __forceinline__ int first_set(uint64_t m) { return __builtin_ctzll(m); }
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// lanes 0..lane inclusive
+__device__ __forceinline__ uint64_t mask_le() { return ~0ull >> (63 - lane_id()); }
+__device__ __forceinline__ uint64_t mask_lt() { return mask_le() >> 1; }
+
+// Inclusive prefix sum over the 64 lanes: four row_shr steps inside each row of 16
+// lanes, then row_bcast:15 and row_bcast:31 carry the row totals upwards.
+__device__ __forceinline__ int scan_incl(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); // row_bcast:15 -> rows 1,3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); // row_bcast:31 -> rows 2,3
+  return x;
+}
+
+// ---------------------------------------------------------------- book storage
+
+template <bool SPILL>
+struct View {
+  int2 *lds;   // [2][3][W]
+  int2 *hbm;   // [2][3][cap]
+  int W, cap;
+  __device__ __forceinline__ int2 *at(int sd, int p, int s) const {
+    if constexpr (!SPILL) {
+      return lds + (sd * 3 + p) * W + s;
+    } else {
+      return s < W ? lds + (sd * 3 + p) * W + s : hbm + (int64_t)(sd * 3 + p) * cap + s;
+    }
+  }
+};
+
+// Wave-uniform state of the book being processed.
+struct State {
+  int n[2];
+  int cap, flags;
+  long long n_msgs, n_trades, limit_qty, market_qty, traded_qty, cancelled_qty, market_discarded,
+      rejected_qty, cancel_miss;
+  int last_ts, last_tns, seen;
+  int32_t *log;        // this book's log segment, or nullptr
+  long long log_count, log_cap;
+  int32_t *fills;      // this book's fills row, or nullptr
+  int fill_cap, fill_count, agent_tid;
+};
+
+// Make the vector-memory stores of this wave visible to its later loads before
+// moving on (only needed when book slots live in HBM).
+template <bool SPILL>
+__device__ __forceinline__ void spill_fence() {
+  if constexpr (SPILL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// Slots [from+m, n) move to [from, n-m).
+template <bool SPILL>
+__device__ void shift_down(const View<SPILL> &B, int sd, int from, int m, int n) {
+  const int l = lane_id();
+  for (int base = from & ~63; base < n - m; base += kWave) {
+    const int s = base + l;
+    const bool act = s >= from && s < n - m;
+    int2 a, b, c;
+    if (act) {
+      a = *B.at(sd, 0, s + m);
+      b = *B.at(sd, 1, s + m);
+      c = *B.at(sd, 2, s + m);
+    }
+    if (act) {
+      *B.at(sd, 0, s) = a;
+      *B.at(sd, 1, s) = b;
+      *B.at(sd, 2, s) = c;
+    }
+    spill_fence<SPILL>();
+  }
+}
+
+// Slots [pos, n) move to [pos+1, n+1); chunks are taken from the top down.
+template <bool SPILL>
+__device__ void shift_up(const View<SPILL> &B, int sd, int pos, int n) {
+  const int l = lane_id();
+  for (int base = (n - 1) & ~63; base >= (pos & ~63); base -= kWave) {
+    const int s = base + l;
+    const bool act = s >= pos && s < n;
+    int2 a, b, c;
+    if (act) {
+      a = *B.at(sd, 0, s);
+      b = *B.at(sd, 1, s);
+      c = *B.at(sd, 2, s);
+    }
+    if (act) {
+      *B.at(sd, 0, s + 1) = a;
+      *B.at(sd, 1, s + 1) = b;
+      *B.at(sd, 2, s + 1) = c;
+    }
+    spill_fence<SPILL>();
+  }
+}
+
+// Store the fills of one matching chunk (lanes with `takes` form the prefix
+// [0, ntr)) to the trade log and, when the book collects them, to the agent fills.
+__device__ __forceinline__ void emit(State &st, bool takes, int ntr, int P, int fill, int pas_oid,
+                                     int agg_oid, int ts, int tns, int pas_tid, int agg_tid) {
+  const int l = lane_id();
+  if (st.log) {
+    const long long room = st.log_cap - st.log_count;
+    if (takes && l < room) {
+      int2 *r = reinterpret_cast<int2 *>(st.log + (st.log_count + l) * kTradeFields);
+      r[0] = make_int2(P, fill);
+      r[1] = make_int2(pas_oid, agg_oid);
+      r[2] = make_int2(ts, tns);
+    }
+    const long long stored = room < ntr ? (room > 0 ? room : 0) : ntr;
+    if (stored < ntr) st.flags |= kFlagTradeFull;
+    st.log_count += stored;
+  }
+  if (st.fills) {
+    const bool ag = takes && (pas_tid == st.agent_tid || agg_tid == st.agent_tid);
+    const uint64_t ma = ballot(ag);
+    if (ma) {
+      const int k = st.fill_count + popc(ma & mask_lt());
+      if (ag && k < st.fill_cap) {
+        int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)k * kTradeFields);
+        r[0] = make_int2(P, fill);
+        r[1] = make_int2(pas_oid, agg_oid);
+        r[2] = make_int2(ts, tns);
+      }
+      st.fill_count += popc(ma);
+    }
+  }
+}
+
+// Matching loop of Section 4.1 for an aggressor on the side opposite to `opp`
+// with limit price `lim` and quantity q.  Returns the unfilled quantity.
+template <bool SPILL>
+__device__ int match(const View<SPILL> &B, State &st, int opp, int lim, int q, int a_oid, int a_tid,
+                     int ts, int tns) {
+  const int l = lane_id();
+  const int n = st.n[opp];
+  const bool buyer = (opp == 0);
+  int removed = 0;
+  for (int base = 0; base < n && q > 0; base += kWave) {
+    const int s = base + l;
+    const bool valid = s < n;
+    int2 pq = make_int2(0, 0);
+    if (valid) pq = *B.at(opp, 0, s);
+    const bool cross = valid && (buyer ? pq.x <= lim : pq.x >= lim);
+    const int qv = cross ? pq.y : 0;
+    const int incl = scan_incl(qv);
+    const int excl = incl - qv;
+    const bool takes = cross && excl < q;
+    const uint64_t mt = ballot(takes);
+    if (mt == 0) break;
+    const int ntr = popc(mt);
+    const bool full = cross && incl <= q;
+    const int nfull = popc(ballot(full));
+    int fill = 0;
+    int2 ot = make_int2(0, 0);
+    if (takes) {
+      fill = min(qv, q - excl);
+      ot = *B.at(opp, 1, s);
+      if (!full) *B.at(opp, 0, s) = make_int2(pq.x, pq.y - fill);
+    }
+    emit(st, takes, ntr, pq.x, fill, ot.x, a_oid, ts, tns, ot.y, a_tid);
+    const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
+    st.traded_qty += consumed;
+    st.n_trades += ntr;
+    q -= consumed;
+    removed += nfull;
+    if (nfull < kWave) break;
+  }
+  spill_fence<SPILL>();
+  if (removed > 0) {
+    shift_down(B, opp, 0, removed, n);
+    st.n[opp] = n - removed;
+  }
+  return q;
+}
+
+// Add (Section 4.1, item 1): the new order goes behind every order with an equal
+// or better price, i.e. at its price-time position.
+template <bool SPILL>
+__device__ void insert(const View<SPILL> &B, State &st, int sd, int P, int Q, int oid, int tid, int ts,
+                       int tns) {
+  const int l = lane_id();
+  const int n = st.n[sd];
+  if (n >= st.cap) {
+    st.rejected_qty += Q;
+    st.flags |= kFlagSideFull;
+    return;
+  }
+  int pos = 0;
+  for (int base = 0; base < n; base += kWave) {
+    const int s = base + l;
+    bool ahead = false;
+    if (s < n) {
+      const int p = B.at(sd, 0, s)->x;
+      ahead = (sd == 1) ? p >= P : p <= P;
+    }
+    const int k = popc(ballot(ahead));
+    pos += k;
+    if (k < kWave) break;
+  }
+  if (pos < n) shift_up(B, sd, pos, n);
+  if (l == 0) {
+    *B.at(sd, 0, pos) = make_int2(P, Q);
+    *B.at(sd, 1, pos) = make_int2(oid, tid);
+    *B.at(sd, 2, pos) = make_int2(ts, tns);
+  }
+  spill_fence<SPILL>();
+  st.n[sd] = n + 1;
+}
+
+// Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders).
+template <bool SPILL>
+__device__ void cancel(const View<SPILL> &B, State &st, int sd, int oid, int qty, int price) {
+  if (qty <= 0) return;
+  const int l = lane_id();
+  const int n = st.n[sd];
+  int k = -1;
+  for (int base = 0; base < n; base += kWave) {
+    const int s = base + l;
+    bool hit = false;
+    if (s < n) hit = B.at(sd, 1, s)->x == oid;
+    const uint64_t m = ballot(hit);
+    if (m) {
+      k = base + first_set(m);
+      break;
+    }
+  }
+  if (k < 0) {
+    for (int base = 0; base < n; base += kWave) {
+      const int s = base + l;
+      bool hit = false;
+      if (s < n) hit = B.at(sd, 1, s)->x <= -9000 && B.at(sd, 0, s)->x == price;
+      const uint64_t m = ballot(hit);
+      if (m) {
+        k = base + first_set(m);
+        break;
+      }
+    }
+  }
+  if (k < 0) {
+    st.cancel_miss++;
+    return;
+  }
+  const int2 pq = *B.at(sd, 0, k);
+  const int P = uni(pq.x), Q = uni(pq.y);
+  st.cancelled_qty += min(qty, Q);
+  const int left = Q - qty;
+  if (left > 0) {
+    if (l == 0) *B.at(sd, 0, k) = make_int2(P, left);
+    spill_fence<SPILL>();
+  } else {
+    shift_down(B, sd, k, 1, n);
+    st.n[sd] = n - 1;
+  }
+}
+
+// L2 of one side: the first L distinct prices with their summed quantities into
+// out[0..L) as (price, qty); missing levels (-1, 0).  `scratch` holds L ints of LDS.
+template <bool SPILL>
+__device__ void l2_side(const View<SPILL> &B, const State &st, int sd, int L, int2 *out, int *scratch) {
+  const int l = lane_id();
+  const int n = st.n[sd];
+  int lv_before = 0, q_before = 0, done = 0;
+  for (int base = 0; base < n && done < L; base += kWave) {
+    const int s = base + l;
+    const bool valid = s < n;
+    int2 pq = make_int2(0, 0);
+    int prev = 0, next = 0;
+    if (valid) {
+      pq = *B.at(sd, 0, s);
+      if (s > 0) prev = B.at(sd, 0, s - 1)->x;
+      if (s + 1 < n) next = B.at(sd, 0, s + 1)->x;
+    }
+    const bool is_new = valid && (s == 0 || prev != pq.x);
+    const bool is_last = valid && (s + 1 == n || next != pq.x);
+    const int incl = q_before + scan_incl(valid ? pq.y : 0);
+    const uint64_t mnew = ballot(is_new);
+    const int lev = lv_before + popc(mnew & mask_le()) - 1;
+    if (is_new && lev < L) scratch[lev] = incl - pq.y;
+    if (is_last && lev < L) out[lev] = make_int2(pq.x, incl - scratch[lev]);
+    lv_before += popc(mnew);
+    done += popc(ballot(is_last));
+    q_before = rdlane(incl, 63);
+  }
+  const int have = done < L ? done : L;
+  if (l >= have && l < L) out[l] = make_int2(-1, 0);
+}
+
+template <bool SPILL>
+__device__ __forceinline__ void write_l2(const View<SPILL> &B, const State &st, int L, int32_t *row,
+                                         int *scratch) {
+  int2 *o = reinterpret_cast<int2 *>(row);
+  l2_side(B, st, 0, L, o, scratch);
+  l2_side(B, st, 1, L, o + L, scratch);
+}
+
+// One message (Section 4.2).  Side index: 0 asks, 1 bids.
+template <bool SPILL>
+__device__ __forceinline__ void process_msg(const View<SPILL> &B, State &st, int T, int S, int P, int Q,
+                                            int oid, int tid, int ts, int tns) {
+  st.n_msgs++;
+  if (T < 1 || T > 4 || (S != 1 && S != -1)) return;
+  if (st.seen && (ts < st.last_ts || (ts == st.last_ts && tns < st.last_tns))) st.flags |= kFlagTimeOrder;
+  st.seen = 1;
+  st.last_ts = ts;
+  st.last_tns = tns;
+  const int own = (S == 1) ? 1 : 0;
+  const int opp = 1 - own;
+  if (T == 1) {
+    if (Q > 0) st.limit_qty += Q;
+    const int rem = match(B, st, opp, P, Q, oid, tid, ts, tns);
+    if (rem > 0) insert(B, st, own, P, rem, oid, tid, ts, tns);
+  } else if (T == 4) {
+    if (Q > 0) st.market_qty += Q;
+    const int rem = match(B, st, opp, S == 1 ? INT_MAX : 0, Q, oid, tid, ts, tns);
+    if (rem > 0) st.market_discarded += rem;
+  } else {
+    cancel(B, st, own, oid, Q, P);
+  }
+}
+
+template <bool SPILL>
+__device__ void process_range(const View<SPILL> &B, State &st, const ProcArgs &a, const int32_t *msgs,
+                              long long beg, long long end, bool l2_each, int *scratch) {
+  const int l = lane_id();
+  for (long long m0 = beg; m0 < end; m0 += kWave) {
+    const int cnt = (int)((end - m0) < kWave ? (end - m0) : kWave);
+    int4 u = make_int4(0, 0, 0, 0), v = make_int4(0, 0, 0, 0);
+    if (l < cnt) {
+      const int4 *mp = reinterpret_cast<const int4 *>(msgs + (m0 + l) * kMsgFields);
+      u = mp[0];
+      v = mp[1];
+    }
+    for (int j = 0; j < cnt; ++j) {
+      const int T = rdlane(u.x, j), S = rdlane(u.y, j), P = rdlane(u.z, j), Q = rdlane(u.w, j);
+      const int oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j), tns = rdlane(v.w, j);
+      process_msg(B, st, T, S, P, Q, oid, tid, ts, tns);
+      if (l2_each) write_l2(B, st, a.levels, a.l2_out + (m0 + j) * 4 * a.levels, scratch);
+    }
+  }
+}
+
+template <bool SPILL>
+__device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
+  const int l = lane_id();
+  const int book = a.book_ids ? uni(a.book_ids[i]) : i;
+  if (book < 0 || book >= a.n_total) return;
+  BookHdr *h = a.hdr + book;
+  State st;
+  st.n[0] = uni(h->n[0]);
+  st.n[1] = uni(h->n[1]);
+  st.cap = uni(h->cap);
+  st.flags = uni(h->flags);
+  st.n_msgs = h->n_msgs;
+  st.n_trades = h->n_trades;
+  st.limit_qty = h->limit_qty;
+  st.market_qty = h->market_qty;
+  st.traded_qty = h->traded_qty;
+  st.cancelled_qty = h->cancelled_qty;
+  st.market_discarded = h->market_discarded;
+  st.rejected_qty = h->rejected_qty;
+  st.cancel_miss = h->cancel_miss;
+  st.last_ts = uni(h->last_ts);
+  st.last_tns = uni(h->last_tns);
+  st.seen = uni(h->seen_time);
+  const long long log_off = h->log_off;
+  st.log_cap = h->log_cap;
+  st.log_count = h->log_count;
+  st.log = a.log ? a.log + log_off * kTradeFields : nullptr;
+  st.fills = a.fills ? a.fills + (int64_t)i * a.fill_cap * kTradeFields : nullptr;
+  st.fill_cap = a.fill_cap;
+  st.fill_count = 0;
+  st.agent_tid = a.agent_tid;
+
+  View<SPILL> B;
+  B.lds = lds;
+  B.hbm = a.books + h->book_off;
+  B.W = a.W;
+  B.cap = st.cap;
+
+  // HBM -> LDS window
+  for (int sd = 0; sd < 2; ++sd) {
+    const int nw = st.n[sd] < a.W ? st.n[sd] : a.W;
+    for (int p = 0; p < 3; ++p)
+      for (int base = 0; base < nw; base += kWave)
+        if (base + l < nw) lds[(sd * 3 + p) * a.W + base + l] = B.hbm[(int64_t)(sd * 3 + p) * st.cap + base + l];
+  }
+
+  if (a.msgs) {
+    long long beg, end;
+    if (a.offs) {
+      beg = a.offs[i];
+      end = a.offs[i + 1];
+    } else {
+      beg = (long long)i * a.w1;
+      end = beg + a.w1;
+    }
+    process_range(B, st, a, a.msgs, beg, end, a.l2_mode == 1, scratch);
+  }
+  if (a.msgs2 && a.w2 > 0) {
+    const long long beg = (long long)i * a.w2;
+    process_range(B, st, a, a.msgs2, beg, beg + a.w2, false, scratch);
+  }
+  if (a.l2_mode == 2) write_l2(B, st, a.levels, a.l2_out + (int64_t)i * 4 * a.levels, scratch);
+
+  // LDS window -> HBM
+  for (int sd = 0; sd < 2; ++sd) {
+    const int nw = st.n[sd] < a.W ? st.n[sd] : a.W;
+    for (int p = 0; p < 3; ++p)
+      for (int base = 0; base < nw; base += kWave)
+        if (base + l < nw) B.hbm[(int64_t)(sd * 3 + p) * st.cap + base + l] = lds[(sd * 3 + p) * a.W + base + l];
+  }
+  if (st.fills) {
+    if (st.fill_count > st.fill_cap) st.flags |= kFlagFillsFull;
+    if (l == 0 && a.fill_counts) a.fill_counts[i] = st.fill_count;
+  }
+  if (l == 0) {
+    h->n[0] = st.n[0];
+    h->n[1] = st.n[1];
+    h->flags = st.flags;
+    h->n_msgs = st.n_msgs;
+    h->n_trades = st.n_trades;
+    h->limit_qty = st.limit_qty;
+    h->market_qty = st.market_qty;
+    h->traded_qty = st.traded_qty;
+    h->cancelled_qty = st.cancelled_qty;
+    h->market_discarded = st.market_discarded;
+    h->rejected_qty = st.rejected_qty;
+    h->cancel_miss = st.cancel_miss;
+    h->last_ts = st.last_ts;
+    h->last_tns = st.last_tns;
+    h->seen_time = st.seen;
+    h->log_count = st.log_count;
+  }
+}
+
+template <bool SPILL>
+__global__ void __launch_bounds__(1024) k_process(ProcArgs a) {
+  extern __shared__ int2 smem[];
+  const int w = threadIdx.x / kWave;
+  const int i = blockIdx.x * a.bpb + w;
+  if (i >= a.n) return;
+  int2 *lds = smem + (int64_t)w * a.lds_int2_per_wave;
+  int *scratch = reinterpret_cast<int *>(lds + 6 * a.W);
+  run_book<SPILL>(a, i, lds, scratch);
+}
+
+// Persistent form: every wave takes listed books from a queue (longest stream
+// first) until the queue is empty.
+template <bool SPILL>
+__global__ void __launch_bounds__(1024) k_process_persistent(ProcArgs a) {
+  extern __shared__ int2 smem[];
+  const int w = threadIdx.x / kWave;
+  int2 *lds = smem + (int64_t)w * a.lds_int2_per_wave;
+  int *scratch = reinterpret_cast<int *>(lds + 6 * a.W);
+  const int qb = a.bucket_range[a.bucket], qe = a.bucket_range[a.bucket + 1];
+  for (;;) {
+    int t = 0;
+    if (lane_id() == 0) t = atomicAdd(a.queue + a.bucket, 1);
+    t = rdlane(t, 0) + qb;
+    if (t >= qe) break;
+    run_book<SPILL>(a, uni(a.order[t]), lds, scratch);
+  }
+}
+
+// ---------------------------------------------------------------- small kernels
+
+__global__ void k_reset(BookHdr *hdr, const int32_t *ids, int n, int n_total) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = ids ? ids[i] : i;
+  if (b < 0 || b >= n_total) return;
+  BookHdr *h = hdr + b;
+  h->n[0] = h->n[1] = 0;
+  h->flags = 0;
+  h->log_count = 0;
+  h->n_msgs = h->n_trades = h->limit_qty = h->market_qty = h->traded_qty = h->cancelled_qty = 0;
+  h->market_discarded = h->rejected_qty = h->cancel_miss = 0;
+  h->last_ts = h->last_tns = 0;
+  h->seen_time = 0;
+}
+
+struct StatusOut {
+  int64_t n_msgs, n_trades, limit_qty, market_qty, traded_qty, cancelled_qty, market_discarded,
+      rejected_qty, cancel_miss;
+  int32_t flags, n_ask, n_bid, pad;
+  int64_t log_records;
+};
+
+__global__ void k_status(const BookHdr *hdr, const int32_t *ids, int n, int n_total, StatusOut *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = ids ? ids[i] : i;
+  StatusOut o;
+  if (b < 0 || b >= n_total) {
+    memset(&o, 0, sizeof(o));
+    o.flags = -1;
+    out[i] = o;
+    return;
+  }
+  const BookHdr *h = hdr + b;
+  o.n_msgs = h->n_msgs;
+  o.n_trades = h->n_trades;
+  o.limit_qty = h->limit_qty;
+  o.market_qty = h->market_qty;
+  o.traded_qty = h->traded_qty;
+  o.cancelled_qty = h->cancelled_qty;
+  o.market_discarded = h->market_discarded;
+  o.rejected_qty = h->rejected_qty;
+  o.cancel_miss = h->cancel_miss;
+  o.flags = h->flags;
+  o.n_ask = h->n[0];
+  o.n_bid = h->n[1];
+  o.pad = 0;
+  o.log_records = h->log_count;
+  out[i] = o;
+}
+
+// L2 straight from the HBM arrays: one wave per listed book, W = 0.
+__global__ void __launch_bounds__(256) k_read_l2(const BookHdr *hdr, int2 *books, const int32_t *ids, int n,
+                                                  int n_total, int L, int32_t *out) {
+  __shared__ int scratch_all[4 * 64];
+  const int w = threadIdx.x / kWave;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= n) return;
+  const int b = ids ? uni(ids[i]) : i;
+  if (b < 0 || b >= n_total) return;
+  const BookHdr *h = hdr + b;
+  View<true> B;
+  B.lds = nullptr;
+  B.hbm = books + h->book_off;
+  B.W = 0;
+  B.cap = uni(h->cap);
+  State st;
+  st.n[0] = uni(h->n[0]);
+  st.n[1] = uni(h->n[1]);
+  write_l2(B, st, L, out + (int64_t)i * 4 * L, scratch_all + w * 64);
+}
+
+// Book dump [n][2][dump_cap][6]: one wave per listed book.
+__global__ void __launch_bounds__(256) k_read_book(const BookHdr *hdr, const int2 *books, const int32_t *ids,
+                                                    int n, int n_total, int dump_cap, int32_t *out) {
+  const int w = threadIdx.x / kWave;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= n) return;
+  const int l = lane_id();
+  const int bid = ids ? uni(ids[i]) : i;
+  if (bid < 0 || bid >= n_total) return;
+  const BookHdr *h = hdr + bid;
+  const int cap = h->cap;
+  const int2 *bk = books + h->book_off;
+  for (int sd = 0; sd < 2; ++sd) {
+    const int live = h->n[sd];
+    int32_t *o = out + ((int64_t)i * 2 + sd) * dump_cap * 6;
+    for (int base = 0; base < dump_cap; base += kWave) {
+      const int s = base + l;
+      if (s >= dump_cap) continue;
+      int2 a = make_int2(-1, -1), b = a, c = a;
+      if (s < live) {
+        a = bk[(sd * 3 + 0) * cap + s];
+        b = bk[(sd * 3 + 1) * cap + s];
+        c = bk[(sd * 3 + 2) * cap + s];
+      }
+      int32_t *r = o + (int64_t)s * 6;
+      r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y; r[4] = c.x; r[5] = c.y;
+    }
+  }
+}
+
+// Load a book dump: rows taken in order up to the first with Q <= 0 or the capacity.
+__global__ void __launch_bounds__(256) k_write_book(BookHdr *hdr, int2 *books, const int32_t *ids, int n,
+                                                     int n_total, int dump_cap, const int32_t *in) {
+  const int w = threadIdx.x / kWave;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= n) return;
+  const int l = lane_id();
+  const int bid = ids ? uni(ids[i]) : i;
+  if (bid < 0 || bid >= n_total) return;
+  BookHdr *h = hdr + bid;
+  const int cap = uni(h->cap);
+  int2 *bk = books + h->book_off;
+  int bad = 0;
+  for (int sd = 0; sd < 2; ++sd) {
+    const int32_t *src = in + ((int64_t)i * 2 + sd) * dump_cap * 6;
+    const int lim = dump_cap < cap ? dump_cap : cap;
+    int live = lim;
+    for (int base = 0; base < lim; base += kWave) {
+      const int s = base + l;
+      const bool stop = s < lim && src[(int64_t)s * 6 + 1] <= 0;
+      const uint64_t m = ballot(stop);
+      if (m) {
+        live = base + first_set(m);
+        break;
+      }
+    }
+    if (live == cap && dump_cap > cap && src[(int64_t)cap * 6 + 1] > 0) bad = 1;
+    for (int base = 0; base < live; base += kWave) {
+      const int s = base + l;
+      bool unsorted = false;
+      if (s < live) {
+        const int32_t *r = src + (int64_t)s * 6;
+        bk[(sd * 3 + 0) * cap + s] = make_int2(r[0], r[1]);
+        bk[(sd * 3 + 1) * cap + s] = make_int2(r[2], r[3]);
+        bk[(sd * 3 + 2) * cap + s] = make_int2(r[4], r[5]);
+        if (s > 0) unsorted = sd == 0 ? r[0] < r[-6] : r[0] > r[-6];
+      }
+      if (ballot(unsorted)) bad = 1;
+    }
+    if (l == 0) h->n[sd] = live;
+  }
+  if (l == 0 && bad) h->flags |= kFlagBadLoad;
+}
+
+// Trade-log drain, pass 1 (one block): counts and exclusive offsets.
+__global__ void __launch_bounds__(1024) k_trade_counts(const BookHdr *hdr, const int32_t *ids, int n,
+                                                        int n_total, int64_t *counts, int64_t *offsets) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b = t * per, e = min(n, b + per);
+  int64_t sum = 0;
+  for (int i = b; i < e; ++i) {
+    const int bid = ids ? ids[i] : i;
+    const int64_t c = (bid >= 0 && bid < n_total) ? hdr[bid].log_count : 0;
+    counts[i] = c;
+    sum += c;
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - sum;
+  for (int i = b; i < e; ++i) {
+    offsets[i] = run;
+    run += counts[i];
+  }
+  if (t == 1023) offsets[n] = part[1023];
+}
+
+// Pass 2 (one block per listed book): copy the records that fit and empty the log.
+__global__ void __launch_bounds__(256) k_trade_copy(BookHdr *hdr, const int32_t *log, const int32_t *ids,
+                                                     int n, int n_total, const int64_t *counts,
+                                                     const int64_t *offsets, int64_t max_records, int32_t *out) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  if (offsets[i + 1] > max_records) return;
+  const int bid = ids ? ids[i] : i;
+  if (bid < 0 || bid >= n_total) return;
+  BookHdr *h = hdr + bid;
+  const int64_t cnt = counts[i];
+  const int2 *src = reinterpret_cast<const int2 *>(log + h->log_off * kTradeFields);
+  int2 *dst = reinterpret_cast<int2 *>(out + offsets[i] * kTradeFields);
+  for (int64_t k = threadIdx.x; k < cnt * 3; k += blockDim.x) dst[k] = src[k];
+  __syncthreads();
+  if (threadIdx.x == 0) h->log_count = 0;
+}
+
+// LPT queue: key = stream length of each listed book (for the persistent kernel);
+// bucket 0 = capacity <= W, bucket 1 = capacity > W (or everything in bucket 0).
+__global__ void k_queue_keys(const BookHdr *hdr, const int32_t *ids, int n, int n_total, const int64_t *offs,
+                             int w1, int W, int split, uint64_t *keys, int32_t *vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t len = offs ? offs[i + 1] - offs[i] : w1;
+  const int bid = ids ? ids[i] : i;
+  const int cap = (bid >= 0 && bid < n_total) ? hdr[bid].cap : 0;
+  const uint64_t bucket = (split && cap > W) ? 1 : 0;
+  // ascending sort: bucket first, then longer streams first
+  const uint64_t inv = (uint64_t)0x00FFFFFFFFFFFFFFull - (uint64_t)(len < 0 ? 0 : len);
+  keys[i] = (bucket << 56) | (inv & 0x00FFFFFFFFFFFFFFull);
+  vals[i] = i;
+}
+
+__global__ void k_queue_ranges(const uint64_t *keys_sorted, int n, int32_t *range, int32_t *queue) {
+  // one thread: range = {0, first index of bucket 1, n}; queue counters zeroed
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) / 2;
+    if ((keys_sorted[mid] >> 56) == 0) lo = mid + 1; else hi = mid;
+  }
+  range[0] = 0;
+  range[1] = lo;
+  range[2] = n;
+  queue[0] = 0;
+  queue[1] = 0;
+}
+
+__global__ void k_selftest(int32_t *out) {
+  // lanes: scan of (lane % 7 + 1), ballot/mask checks
+  const int l = lane_id();
+  const int v = l % 7 + 1;
+  out[l] = scan_incl(v);
+  out[64 + l] = popc(ballot(l % 3 == 0) & mask_le());
+  out[128 + l] = popc(mask_lt());
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_process(const ProcArgs &a, bool spill, bool persistent, int blocks, hipStream_t s) {
+  const int threads = a.bpb * kWave;
+  const size_t lds = (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2);
+  if (persistent) {
+    if (spill)
+      hipLaunchKernelGGL(k_process_persistent<true>, dim3(blocks), dim3(threads), lds, s, a);
+    else
+      hipLaunchKernelGGL(k_process_persistent<false>, dim3(blocks), dim3(threads), lds, s, a);
+  } else {
+    const int grid = (a.n + a.bpb - 1) / a.bpb;
+    if (spill)
+      hipLaunchKernelGGL(k_process<true>, dim3(grid), dim3(threads), lds, s, a);
+    else
+      hipLaunchKernelGGL(k_process<false>, dim3(grid), dim3(threads), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t set_process_lds_limit(size_t bytes) {
+  hipError_t e = hipSuccess;
+  e = hipFuncSetAttribute((const void *)k_process<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_process<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_process_persistent<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_process_persistent<false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t occupancy_persistent(bool spill, int threads, size_t lds, int *blocks_per_cu) {
+  if (spill)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_process_persistent<true>, threads, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_process_persistent<false>, threads, lds);
+}
+
+hipError_t launch_reset(BookHdr *hdr, const int32_t *ids, int n, int n_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, hdr, ids, n, n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_status(const BookHdr *hdr, const int32_t *ids, int n, int n_total, void *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_status, dim3((n + 255) / 256), dim3(256), 0, s, hdr, ids, n, n_total,
+                     reinterpret_cast<StatusOut *>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_read_l2(const BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
+                          int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_read_l2, dim3((n + 3) / 4), dim3(256), 0, s, hdr, books, ids, n, n_total, L, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_book(const BookHdr *hdr, const int2 *books, const int32_t *ids, int n, int n_total,
+                            int dump_cap, int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_read_book, dim3((n + 3) / 4), dim3(256), 0, s, hdr, books, ids, n, n_total, dump_cap,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_book(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int dump_cap,
+                             const int32_t *in, hipStream_t s) {
+  hipLaunchKernelGGL(k_write_book, dim3((n + 3) / 4), dim3(256), 0, s, hdr, books, ids, n, n_total, dump_cap,
+                     in);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *ids, int n, int n_total,
+                              int32_t *out, int64_t max_records, int64_t *counts, int64_t *offsets,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_trade_counts, dim3(1), dim3(1024), 0, s, hdr, ids, n, n_total, counts, offsets);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  hipLaunchKernelGGL(k_trade_copy, dim3(n), dim3(256), 0, s, hdr, log, ids, n, n_total, counts, offsets,
+                     max_records, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_keys(const BookHdr *hdr, const int32_t *ids, int n, int n_total, const int64_t *offs,
+                             int w1, int W, int split, uint64_t *keys, int32_t *vals, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_keys, dim3((n + 255) / 256), dim3(256), 0, s, hdr, ids, n, n_total, offs, w1, W,
+                     split, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_ranges(const uint64_t *keys_sorted, int n, int32_t *range, int32_t *queue,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_ranges, dim3(1), dim3(64), 0, s, keys_sorted, n, range, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_selftest(int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_selftest, dim3(1), dim3(64), 0, s, out);
+  return hipGetLastError();
+}
+
+}  // namespace lob

@@ -1,0 +1,249 @@
+"""Python binding of liblob (include/lob.h).
+
+Argument marshalling only: every step of the matching path runs in the HIP
+kernels of liblob.so.  torch provides device memory (tensors) and streams.
+The library must be built (paper_2308_13289_amd.build); without it every call
+raises LobError -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblob.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ECAP = 0, -1, -2, -3, -6
+L2_NONE, L2_PER_MESSAGE, L2_FINAL = 0, 1, 2
+BOOK_SIDE_FULL, BOOK_TIME_ORDER, BOOK_TRADE_FULL, BOOK_FILLS_FULL, BOOK_BAD_LOAD = 1, 2, 4, 8, 16
+
+STATUS_DTYPE = np.dtype([(n, np.int64) for n in (
+    "n_msgs", "n_trades", "limit_qty", "market_qty", "traded_qty", "cancelled_qty",
+    "market_discarded", "rejected_qty", "cancel_miss")] + [
+    ("flags", np.int32), ("n_ask", np.int32), ("n_bid", np.int32), ("pad", np.int32),
+    ("log_records", np.int64)])
+assert STATUS_DTYPE.itemsize == 96
+
+
+class LobError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"liblob status {status}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_books", ctypes.c_int32), ("capacity_host", ctypes.POINTER(ctypes.c_int32)),
+                ("l2_levels", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("trade_log_records_host", ctypes.POINTER(ctypes.c_int64)),
+                ("trade_log_default", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("lds_slots", ctypes.c_int32), ("books_per_block", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("split_buckets", ctypes.c_int32), ("lds_slots_big", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+_lib = None
+EXPORTS = ["lob_create", "lob_destroy", "lob_last_error", "lob_info", "lob_set_plan", "lob_get_plan",
+           "lob_process_messages", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
+           "lob_read_book", "lob_write_book", "lob_reset", "lob_selftest"]
+
+
+def load(path=None):
+    """Load liblob.so and declare its signatures (no GPU is touched)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise LobError(EINVAL, f"{p} is not built (python -m paper_2308_13289_amd.build)")
+    L = ctypes.CDLL(p)
+    vp, i32, i64, P32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)
+    L.lob_create.restype = i32
+    L.lob_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(vp)]
+    L.lob_destroy.restype = None
+    L.lob_destroy.argtypes = [vp]
+    L.lob_last_error.restype = ctypes.c_char_p
+    L.lob_last_error.argtypes = [vp]
+    L.lob_info.restype = i32
+    L.lob_info.argtypes = [vp, P32, P32, P32]
+    L.lob_set_plan.restype = i32
+    L.lob_set_plan.argtypes = [vp, ctypes.POINTER(Plan)]
+    L.lob_get_plan.restype = i32
+    L.lob_get_plan.argtypes = [vp, ctypes.POINTER(Plan)]
+    L.lob_process_messages.restype = i32
+    L.lob_process_messages.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
+    L.lob_step.restype = i32
+    L.lob_step.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, i32, vp, vp]
+    L.lob_read_l2.restype = i32
+    L.lob_read_l2.argtypes = [vp, vp, i32, vp, vp]
+    L.lob_read_trades.restype = i32
+    L.lob_read_trades.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp]
+    L.lob_read_status.restype = i32
+    L.lob_read_status.argtypes = [vp, vp, i32, vp, vp]
+    L.lob_read_book.restype = i32
+    L.lob_read_book.argtypes = [vp, vp, i32, vp, i32, vp]
+    L.lob_write_book.restype = i32
+    L.lob_write_book.argtypes = [vp, vp, i32, vp, i32, vp]
+    L.lob_reset.restype = i32
+    L.lob_reset.argtypes = [vp, vp, i32, vp]
+    L.lob_selftest.restype = i32
+    L.lob_selftest.argtypes = [i32, vp, vp]
+    if path is None:
+        _lib = L
+    return L
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def selftest(device=0):
+    out = torch.empty(192, dtype=torch.int32, device=f"cuda:{device}")
+    st = load().lob_selftest(device, _ptr(out), _stream(None, out.device))
+    if st != OK:
+        raise LobError(st, "selftest launch failed")
+    return out
+
+
+class Context:
+    """A set of books resident on one GPU (lob_create / lob_destroy)."""
+
+    def __init__(self, capacities, l2_levels=10, device=0, trade_log_records=None,
+                 trade_log_default=0):
+        self._lib = load()
+        caps = np.ascontiguousarray(capacities, dtype=np.int32)
+        self.capacities = caps
+        self.device = torch.device(f"cuda:{device}")
+        self.levels = int(l2_levels)
+        cfg = Config()
+        cfg.n_books = caps.shape[0]
+        cfg.capacity_host = caps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        cfg.l2_levels = self.levels
+        cfg.device = device
+        self._logs = None
+        if trade_log_records is not None:
+            self._logs = np.ascontiguousarray(trade_log_records, dtype=np.int64)
+            cfg.trade_log_records_host = self._logs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        cfg.trade_log_default = int(trade_log_default)
+        cfg.flags = 0
+        h = ctypes.c_void_p()
+        st = self._lib.lob_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != OK:
+            raise LobError(st, self._lib.lob_last_error(None).decode())
+        self._h = h
+        self.n_books = int(caps.shape[0])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lob_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise LobError(st, self._lib.lob_last_error(self._h).decode())
+
+    def _ids(self, book_ids, n):
+        if book_ids is None:
+            return None, (self.n_books if n is None else int(n))
+        return _ptr(book_ids, torch.int32, "book_ids"), int(book_ids.numel())
+
+    # -- plan
+    def get_plan(self):
+        p = Plan()
+        self._check(self._lib.lob_get_plan(self._h, ctypes.byref(p)))
+        return p
+
+    def set_plan(self, **kw):
+        p = self.get_plan()
+        for k, v in kw.items():
+            setattr(p, k, int(v))
+        self._check(self._lib.lob_set_plan(self._h, ctypes.byref(p)))
+        return p
+
+    # -- matching
+    def process(self, msgs, offsets, book_ids=None, l2_mode=L2_NONE, l2_out=None, stream=None):
+        ids, n = self._ids(book_ids, offsets.numel() - 1)
+        self._check(self._lib.lob_process_messages(
+            self._h, ids, n, _ptr(msgs, torch.int32, "msgs"), _ptr(offsets, torch.int64, "offsets"),
+            l2_mode, _ptr(l2_out, torch.int32, "l2_out"), _stream(stream, self.device)))
+
+    def step(self, window, l2_out, actions=None, book_ids=None, agent_tid=-1, fills=None,
+             fill_counts=None, stream=None):
+        n = window.shape[0]
+        ids, n = self._ids(book_ids, n)
+        W = window.shape[1]
+        A = 0 if actions is None else actions.shape[1]
+        F = 0 if fills is None else fills.shape[1]
+        self._check(self._lib.lob_step(
+            self._h, ids, n, _ptr(window, torch.int32, "window"), W,
+            _ptr(actions, torch.int32, "actions"), A, agent_tid, _ptr(l2_out, torch.int32, "l2_out"),
+            _ptr(fills, torch.int32, "fills"), F, _ptr(fill_counts, torch.int32, "fill_counts"),
+            _stream(stream, self.device)))
+
+    # -- readouts
+    def read_l2(self, book_ids=None, out=None, stream=None):
+        ids, n = self._ids(book_ids, None)
+        if out is None:
+            out = torch.empty((n, 2, self.levels, 2), dtype=torch.int32, device=self.device)
+        self._check(self._lib.lob_read_l2(self._h, ids, n, _ptr(out, torch.int32, "out"),
+                                          _stream(stream, self.device)))
+        return out
+
+    def read_trades(self, max_records, book_ids=None, out=None, stream=None):
+        """Returns (records [max_records, 6], counts [n], offsets [n+1]) device tensors."""
+        ids, n = self._ids(book_ids, None)
+        if out is None:
+            out = torch.empty((max(int(max_records), 1), 6), dtype=torch.int32, device=self.device)
+        counts = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        self._check(self._lib.lob_read_trades(
+            self._h, ids, n, _ptr(out, torch.int32, "out"), int(max_records), _ptr(counts), _ptr(offsets),
+            _stream(stream, self.device)))
+        return out, counts[:n], offsets
+
+    def read_status(self, book_ids=None, stream=None):
+        """numpy structured array (STATUS_DTYPE) of per-book counters; synchronizes."""
+        ids, n = self._ids(book_ids, None)
+        buf = torch.empty(max(n, 1) * STATUS_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        self._check(self._lib.lob_read_status(self._h, ids, n, _ptr(buf), _stream(stream, self.device)))
+        return buf.cpu().numpy()[:n * STATUS_DTYPE.itemsize].view(STATUS_DTYPE)
+
+    def read_book(self, dump_cap=None, book_ids=None, out=None, stream=None):
+        ids, n = self._ids(book_ids, None)
+        dump_cap = int(dump_cap or self.capacities.max())
+        if out is None:
+            out = torch.empty((n, 2, dump_cap, 6), dtype=torch.int32, device=self.device)
+        self._check(self._lib.lob_read_book(self._h, ids, n, _ptr(out, torch.int32, "out"), dump_cap,
+                                            _stream(stream, self.device)))
+        return out
+
+    def write_book(self, dump, book_ids=None, stream=None):
+        ids, n = self._ids(book_ids, dump.shape[0])
+        self._check(self._lib.lob_write_book(self._h, ids, n, _ptr(dump, torch.int32, "dump"),
+                                             int(dump.shape[2]), _stream(stream, self.device)))
+
+    def reset(self, book_ids=None, stream=None):
+        ids, n = self._ids(book_ids, None)
+        self._check(self._lib.lob_reset(self._h, ids, n, _stream(stream, self.device)))

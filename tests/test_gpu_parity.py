@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit for bit.
+
+Every record is int32, so every comparison is exact: trades per book in order,
+final books (canonical priority-ordered dumps), L2 snapshots and counters.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():  # pragma: no cover - collected on CPU hosts too
+    pytest.skip("no GPU", allow_module_level=True)
+
+from golden_cases import all_cases  # noqa: E402
+from gpu_helpers import assert_same, new_context, run_gpu, run_oracle, to_dev  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+from paper_2308_13289_amd import lob  # noqa: E402
+from paper_2308_13289_amd import workload as W  # noqa: E402
+from test_oracle_bruteforce import alphabet, to_msgs  # noqa: E402
+
+
+def test_selftest_primitives():
+    out = lob.selftest().cpu().numpy()
+    lanes = np.arange(64)
+    np.testing.assert_array_equal(out[:64], np.cumsum(lanes % 7 + 1))
+    np.testing.assert_array_equal(out[64:128], np.cumsum(lanes % 3 == 0))
+    np.testing.assert_array_equal(out[128:192], lanes)
+
+
+def test_golden_cases_on_gpu():
+    cases = all_cases()
+    caps = np.array([c.cap for c in cases], np.int32)
+    msgs = np.concatenate([c.msgs for c in cases])
+    offs = np.concatenate([[0], np.cumsum([len(c.msgs) for c in cases])]).astype(np.int64)
+    g = run_gpu(caps, msgs, offs, levels=3, l2_mode=lob.L2_FINAL)
+    for i, c in enumerate(cases):
+        tr = g["trades"][g["trade_offs"][i]:g["trade_offs"][i + 1]]
+        np.testing.assert_array_equal(tr, c.trades[:, 1:].astype(np.int32), err_msg=c.name)
+        d = g["dumps"][i]
+        np.testing.assert_array_equal(d[0][:len(c.ask)], c.ask, err_msg=c.name)
+        np.testing.assert_array_equal(d[1][:len(c.bid)], c.bid, err_msg=c.name)
+        assert (d[0][len(c.ask):] == -1).all() and (d[1][len(c.bid):] == -1).all(), c.name
+        if c.l2ask is not None:
+            np.testing.assert_array_equal(g["l2"][i][0], c.l2ask, err_msg=c.name)
+        if c.l2bid is not None:
+            np.testing.assert_array_equal(g["l2"][i][1], c.l2bid, err_msg=c.name)
+        for k, v in c.stats.items():
+            assert g["status"][k][i] == v, (c.name, k)
+
+
+@pytest.mark.parametrize("cap", [1, 2])
+def test_bruteforce_sequences_on_gpu(cap):
+    streams = [to_msgs(s) for s in itertools.product(alphabet(), repeat=3)]
+    msgs = np.array([m for s in streams for m in s], np.int32)
+    offs = np.concatenate([[0], np.cumsum([len(s) for s in streams])]).astype(np.int64)
+    caps = np.full(len(streams), cap, np.int32)
+    g = run_gpu(caps, msgs, offs, levels=2, l2_mode=lob.L2_PER_MESSAGE)
+    o = run_oracle(caps, msgs, offs, levels=2, l2_mode=O.L2_PER_MESSAGE)
+    assert_same(g, o, f"brute force cap {cap}")
+
+
+def test_c0_full_parity_per_message_l2():
+    """64 books x (100 seeds + 1000 messages), capacity 100, L2 after every message."""
+    w = W.c0()
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_PER_MESSAGE)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_PER_MESSAGE)
+    assert_same(g, o, "c0")
+    assert o["stats"]["n_trades"].sum() > 30000
+
+
+@pytest.mark.parametrize("plan", [
+    {"books_per_block": 1},
+    {"books_per_block": 8},
+    {"persistent": 1},
+    {"lds_slots": 64},                      # books past 64 orders spill to HBM
+    {"lds_slots": 64, "persistent": 1},
+], ids=["bpb1", "bpb8", "persistent", "spill64", "spill64_persistent"])
+def test_plans_agree_c0(plan):
+    w = W.c0()
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
+    assert_same(g, o, str(plan))
+
+
+@pytest.mark.parametrize("plan", [
+    {},
+    {"lds_slots": 128},
+    {"persistent": 1},
+    {"persistent": 1, "lds_slots": 128, "split_buckets": 1, "lds_slots_big": 1000},
+    {"persistent": 1, "lds_slots": 128, "split_buckets": 1, "lds_slots_big": 256},
+], ids=["default", "spill128", "persistent", "split", "split_spill"])
+def test_ragged_mixed_capacities(plan):
+    """Capacities {50,100,500,1000} and uneven stream lengths in one call."""
+    w = W.ragged(n_books=96, max_flow=4000)
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
+    assert_same(g, o, f"ragged {plan}")
+
+
+def test_small_capacity_rejects_and_deep_books():
+    """Capacity 8 (sides fill up and reject) and capacity 300 with a one-sided flow
+    that keeps > 64 orders resting (multi-chunk shifts, scans and L2)."""
+    a = W.uniform(16, 3000, cap=8, tag=90)
+    g = run_gpu(a.caps, a.msgs, a.offs, l2_mode=lob.L2_PER_MESSAGE)
+    o = run_oracle(a.caps, a.msgs, a.offs, l2_mode=O.L2_PER_MESSAGE)
+    assert_same(g, o, "cap 8")
+    assert o["stats"]["rejected_qty"].sum() > 0
+    rng = np.random.default_rng(7)
+    streams = []
+    for b in range(8):
+        ms, t = [], 0
+        for k in range(260):  # bids at many prices, some repeated
+            ms.append([1, 1, int(rng.integers(900, 1000)), int(rng.integers(1, 50)), k + 1, 3, 34200, t])
+            t += 1
+        for k in range(40):  # cancels of live and dead ids, then sweeping sells
+            ms.append([2, 1, 0, int(rng.integers(1, 30)), int(rng.integers(1, 260)), 3, 34200, t])
+            t += 1
+        for k in range(6):
+            ms.append([1, -1, int(rng.integers(900, 1000)), int(rng.integers(50, 3000)), 1000 + k, 4, 34200, t])
+            t += 1
+        ms.append([4, -1, 0, 5000, 2000, 4, 34200, t])
+        streams.append(ms)
+    msgs = np.array([m for s in streams for m in s], np.int32)
+    offs = np.concatenate([[0], np.cumsum([len(s) for s in streams])]).astype(np.int64)
+    caps = np.full(8, 300, np.int32)
+    for plan in ({}, {"lds_slots": 64}):
+        g = run_gpu(caps, msgs, offs, l2_mode=lob.L2_PER_MESSAGE, plan=plan)
+        o = run_oracle(caps, msgs, offs, l2_mode=O.L2_PER_MESSAGE)
+        assert_same(g, o, f"deep books {plan}")
+
+
+def test_split_calls_equal_one_call():
+    """Book state stays on the device between calls: three calls = one call."""
+    w = W.uniform(48, 1500, tag=93)
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_PER_MESSAGE, calls=3)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_PER_MESSAGE)
+    assert_same(g, o, "3 calls")
+
+
+def test_checkpoint_resume():
+    """read_book after half of the stream, write_book into a fresh context, finish
+    there: the rest of the trades and the final books match the oracle."""
+    w = W.uniform(32, 2000, tag=94)
+    lens = np.diff(w.offs)
+    half = w.offs[:-1] + lens // 2
+    first = np.concatenate([np.arange(a, b) for a, b in zip(w.offs[:-1], half)])
+    second = np.concatenate([np.arange(a, b) for a, b in zip(half, w.offs[1:])])
+    offs1 = np.concatenate([[0], np.cumsum(half - w.offs[:-1])]).astype(np.int64)
+    offs2 = np.concatenate([[0], np.cumsum(w.offs[1:] - half)]).astype(np.int64)
+    ctx1 = new_context(w.caps, 10, lens)
+    ctx1.process(to_dev(w.msgs[first]), to_dev(offs1))
+    dump = ctx1.read_book(100)
+    ctx2 = new_context(w.caps, 10, lens)
+    ctx2.write_book(dump)
+    g = run_gpu(w.caps, w.msgs[second], offs2, l2_mode=lob.L2_FINAL, ctx=ctx2)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
+    np.testing.assert_array_equal(g["dumps"], o["dumps"])
+    np.testing.assert_array_equal(g["l2"], o["l2"])
+    ofull = O.run(w.caps, w.msgs, w.offs)
+    # trades of the second half: the oracle's trades minus those of the first half
+    o1 = O.run(w.caps, w.msgs[first], offs1)
+    for i in range(w.n_books):
+        want = ofull["trades"][ofull["trade_offs"][i] + o1["trade_counts"][i]:ofull["trade_offs"][i + 1], :6]
+        got = g["trades"][g["trade_offs"][i]:g["trade_offs"][i + 1]]
+        np.testing.assert_array_equal(got, want)
+    assert (g["status"]["flags"] & lob.BOOK_BAD_LOAD == 0).all()
+
+
+def test_read_trades_drains_only_what_fits():
+    w = W.uniform(8, 300, tag=95)
+    ctx = new_context(w.caps, 10, np.diff(w.offs))
+    ctx.process(to_dev(w.msgs), to_dev(w.offs))
+    o = O.run(w.caps, w.msgs, w.offs)
+    counts = o["trade_counts"]
+    k = 3
+    room = int(counts[:k].sum()) + 1  # the first 3 books fit, the 4th does not
+    rec, cnt, offs = ctx.read_trades(room)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(cnt.cpu().numpy(), counts)
+    assert int(offs[-1]) == counts.sum()
+    np.testing.assert_array_equal(rec[:int(counts[:k].sum())].cpu().numpy(),
+                                  o["trades"][:o["trade_offs"][k], :6])
+    st = ctx.read_status()
+    assert (st["log_records"][:k] == 0).all()
+    np.testing.assert_array_equal(st["log_records"][k:], counts[k:])
+    rec2, cnt2, offs2 = ctx.read_trades(int(counts.sum()))
+    torch.cuda.synchronize()
+    c2 = cnt2.cpu().numpy()
+    assert (c2[:k] == 0).all()
+    np.testing.assert_array_equal(rec2[:int(c2.sum())].cpu().numpy(), o["trades"][o["trade_offs"][k]:, :6])
+
+
+def test_trade_log_full_is_flagged():
+    w = W.uniform(4, 2000, tag=96)
+    ctx = new_context(w.caps, 10, log_room=np.full(4, 50, np.int64))
+    ctx.process(to_dev(w.msgs), to_dev(w.offs))
+    st = ctx.read_status()
+    o = O.run(w.caps, w.msgs, w.offs)
+    assert (st["flags"] & lob.BOOK_TRADE_FULL).all()
+    np.testing.assert_array_equal(st["log_records"], np.full(4, 50))
+    np.testing.assert_array_equal(st["n_trades"], o["trade_counts"])
+    rec, _, _ = ctx.read_trades(200)
+    torch.cuda.synchronize()
+    want = np.concatenate([o["trades"][o["trade_offs"][i]:o["trade_offs"][i] + 50, :6] for i in range(4)])
+    np.testing.assert_array_equal(rec[:200].cpu().numpy(), want)
+
+
+def test_edge_inputs():
+    # zero books, books with no messages, padding only, decreasing time
+    ctx = new_context([4, 4, 4], 3, log_room=[16, 16, 16])
+    ctx.process(to_dev(np.zeros((0, 8), np.int32)), to_dev(np.zeros(1, np.int64)))
+    msgs = np.array([[0] * 8, [0, 1, 5, 5, 1, 1, 1, 1],
+                     [1, 1, 100, 5, 1, 0, 10, 5], [1, 1, 101, 5, 2, 0, 10, 4]], np.int32)
+    offs = np.array([0, 0, 2, 4], np.int64)
+    ctx.process(to_dev(msgs), to_dev(offs))
+    st = ctx.read_status()
+    assert list(st["n_msgs"]) == [0, 2, 2]
+    assert st["flags"][2] & lob.BOOK_TIME_ORDER and not st["flags"][1]
+    np.testing.assert_array_equal(st["n_bid"], [0, 0, 2])
+    with pytest.raises(lob.LobError):
+        ctx.process(to_dev(msgs), to_dev(np.array([0, 1, 2, 3, 4], np.int64)))  # 4 books > 3
+
+
+def test_reset_and_book_ids_subset():
+    w = W.uniform(16, 800, tag=97)
+    ctx = new_context(w.caps, 10, np.diff(w.offs) * 2)
+    ids = np.arange(1, 16, 2, dtype=np.int32)
+    sel = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in ids])
+    soffs = np.concatenate([[0], np.cumsum(np.diff(w.offs)[ids])]).astype(np.int64)
+    ctx.process(to_dev(w.msgs[sel]), to_dev(soffs), book_ids=to_dev(ids))
+    st = ctx.read_status()
+    assert (st["n_msgs"][ids] > 0).all() and (st["n_msgs"][ids - 1] == 0).all()
+    ctx.reset()
+    st = ctx.read_status()
+    assert (st["n_msgs"] == 0).all() and (st["n_bid"] == 0).all() and (st["log_records"] == 0).all()
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, ctx=ctx)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
+    assert_same(g, o, "after reset")
+
+
+def test_deterministic_repeat():
+    w = W.ragged(n_books=64, max_flow=3000)
+    a = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan={"persistent": 1})
+    b = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan={"persistent": 1})
+    for k in ("trades", "trade_offs", "dumps", "l2"):
+        np.testing.assert_array_equal(a[k], b[k])
