@@ -19,7 +19,8 @@
  *     times going backwards) never fail a call: they are counted per book and
  *     read with lob_read_status.
  *   - A context is used by one host thread at a time.  A book id may appear at
- *     most once in one call; calls on one stream are processed in order.
+ *     most once in one call; calls on one stream are processed in order.  Book ids
+ *     in device arrays outside [0, n_books) are skipped.
  *   - Every field of every record is int32: prices in ticks, quantities in shares,
  *     ids, and times split into whole seconds and nanoseconds (Section 4.2).
  *
@@ -111,22 +112,22 @@ typedef struct {
   int64_t log_records;      /* trades waiting in the book's log                  */
 } lob_book_status;
 
-/* Execution plan (lob_set_plan); lob_autotune picks one by measurement. */
+/* Execution plan (lob_set_plan).  Results never depend on the plan, only speed. */
 typedef struct {
-  int32_t lds_slots;       /* orders per side kept in LDS, a multiple of 64 in
-                              64..4096; a book with a larger capacity keeps the
-                              orders past this many in HBM                      */
+  int32_t lds_slots;       /* orders per side kept in LDS by lob_process_messages and
+                              lob_step launches, 1..4096; a book with a larger
+                              capacity keeps the orders past this many in HBM     */
   int32_t books_per_block; /* wavefronts (one book each) per workgroup, 1..16    */
-  int32_t persistent;      /* 0: one wavefront per listed book;
-                              1: persistent wavefronts take books from a device
-                              queue, longest message stream first              */
-  int32_t waves_per_cu;    /* persistent mode: wavefronts launched per compute
-                              unit, 0 = as many as LDS and registers allow      */
-  int32_t split_buckets;   /* persistent mode, 1: books whose capacity fits in
-                              lds_slots and books that do not run as two queues
-                              in two concurrent launches; the second keeps
-                              lds_slots_big orders per side in LDS              */
-  int32_t lds_slots_big;   /* LDS window of the second launch (>= lds_slots)     */
+  int32_t ragged_split;    /* lob_process_ragged: 0 = one launch with window
+                              lds_slots; > 0 = books of capacity <= ragged_split
+                              run in one launch with window ragged_split, the
+                              others concurrently in a second launch with window
+                              lds_slots_big                                     */
+  int32_t lds_slots_big;   /* window of the second ragged launch, 1..4096        */
+  int32_t ragged_order;    /* lob_process_ragged: 1 = longest stream first
+                              (longest-processing-time list scheduling), 0 = as
+                              listed                                            */
+  int32_t books_per_block_big; /* books per workgroup of the second ragged launch */
   int32_t reserved[2];
 } lob_plan;
 
@@ -166,6 +167,23 @@ lob_status lob_get_plan(const lob_ctx *ctx, lob_plan *plan);
 lob_status lob_process_messages(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
                                 const int32_t *msgs, const int64_t *msg_offsets,
                                 int32_t l2_mode, int32_t *l2_out, void *stream);
+
+/* Ragged batches: books of uneven capacity and stream length in one call.  Same
+ * results as lob_process_messages; the host also receives the stream bounds, so
+ * the library can order the books longest stream first and split them into
+ * capacity buckets that run concurrently (see lob_plan).  The workgroup dispatcher
+ * hands each next book to the first free SIMD.
+ *   book_ids_host [n_books]   host array of distinct book ids (NULL: 0..n-1),
+ *                             checked on the host (LOB_EINVAL if out of range or
+ *                             repeated)
+ *   msg_offsets_host [n+1]    host array: listed book i processes
+ *                             msgs[msg_offsets_host[i] .. msg_offsets_host[i+1])
+ *   l2_mode, l2_out           as lob_process_messages (rows keep the listed order)
+ * Waits for the host-to-device copy of the schedule of the previous ragged call
+ * on this context before reusing its staging buffer. */
+lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books,
+                              const int32_t *msgs, const int64_t *msg_offsets_host,
+                              int32_t l2_mode, int32_t *l2_out, void *stream);
 
 /* One environment step per listed book (Section 5.1.3): the W data messages of
  * window[i] (zero padding skipped), then the A agent messages of actions[i]

@@ -5,7 +5,6 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
-#include <hipcub/hipcub.hpp>
 #include <string>
 #include <vector>
 
@@ -13,9 +12,8 @@
 #include "lob_internal.h"
 
 namespace lob {
-hipError_t launch_process(const ProcArgs &a, bool spill, bool persistent, int blocks, hipStream_t s);
+hipError_t launch_process(const ProcArgs &a, bool spill, hipStream_t s);
 hipError_t set_process_lds_limit(size_t bytes);
-hipError_t occupancy_persistent(bool spill, int threads, size_t lds, int *blocks_per_cu);
 hipError_t launch_reset(BookHdr *hdr, const int32_t *ids, int n, int n_total, hipStream_t s);
 hipError_t launch_status(const BookHdr *hdr, const int32_t *ids, int n, int n_total, void *out, hipStream_t s);
 hipError_t launch_read_l2(const BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
@@ -27,10 +25,6 @@ hipError_t launch_write_book(BookHdr *hdr, int2 *books, const int32_t *ids, int 
 hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *ids, int n, int n_total,
                               int32_t *out, int64_t max_records, int64_t *counts, int64_t *offsets,
                               hipStream_t s);
-hipError_t launch_queue_keys(const BookHdr *hdr, const int32_t *ids, int n, int n_total, const int64_t *offs,
-                             int w1, int W, int split, uint64_t *keys, int32_t *vals, hipStream_t s);
-hipError_t launch_queue_ranges(const uint64_t *keys_sorted, int n, int32_t *range, int32_t *queue,
-                               hipStream_t s);
 hipError_t launch_selftest(int32_t *out, hipStream_t s);
 }  // namespace lob
 
@@ -47,11 +41,14 @@ struct lob_ctx {
   std::string err;
   int num_cus = 0;
   size_t max_lds = 0;
-  // persistent-queue workspace
-  uint64_t *d_keys = nullptr, *d_keys_sorted = nullptr;
-  int32_t *d_vals = nullptr, *d_order = nullptr, *d_range = nullptr, *d_queue = nullptr;
-  void *d_sort_tmp = nullptr;
-  size_t sort_tmp_bytes = 0;
+  // ragged schedule: listed ids, message ranges and output rows of one call, staged
+  // in pinned host memory and copied to the device in one transfer
+  int32_t *h_stage = nullptr, *d_stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t ev_staged = nullptr;  // the last staging copy has completed
+  bool staged_pending = false;
+  hipEvent_t ev_ragged_done = nullptr;  // all work of the last ragged call
+  bool ragged_pending = false;
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
@@ -92,13 +89,10 @@ void free_ctx(lob_ctx *c) {
   (void)hipFree(c->d_hdr);
   (void)hipFree(c->d_books);
   (void)hipFree(c->d_log);
-  (void)hipFree(c->d_keys);
-  (void)hipFree(c->d_keys_sorted);
-  (void)hipFree(c->d_vals);
-  (void)hipFree(c->d_order);
-  (void)hipFree(c->d_range);
-  (void)hipFree(c->d_queue);
-  (void)hipFree(c->d_sort_tmp);
+  (void)hipFree(c->d_stage);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->ev_staged) (void)hipEventDestroy(c->ev_staged);
+  if (c->ev_ragged_done) (void)hipEventDestroy(c->ev_ragged_done);
   if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
@@ -137,79 +131,20 @@ lob_status geometry(lob_ctx *c, int window, int cap_limit, int bpb_want, Geometr
   return LOB_OK;
 }
 
-lob_status run_process(lob_ctx *c, lob::ProcArgs a, hipStream_t s) {
+lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bpb, hipStream_t s) {
   if (a.n == 0) return LOB_OK;
-  const lob_plan &p = c->plan;
   Geometry g;
-  lob_status st = geometry(c, p.lds_slots, c->max_cap, p.books_per_block, &g);
+  lob_status st = geometry(c, window, cap_limit, bpb, &g);
   if (st != LOB_OK) return st;
   a.W = g.W;
   a.bpb = g.bpb;
   a.lds_int2_per_wave = g.per_wave;
-  if (!p.persistent) {
-    hipError_t e = lob::launch_process(a, g.spill, false, 0, s);
-    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
-  }
-  // persistent: queue of listed books, longest stream first, in one or two buckets
-  const bool split = p.split_buckets && c->max_cap > g.W;
-  hipError_t e = lob::launch_queue_keys(c->d_hdr, a.book_ids, a.n, c->n_books, a.offs, a.w1, g.W, split ? 1 : 0, c->d_keys,
-                                        c->d_vals, s);
-  if (e != hipSuccess) return hip_fail(c, e, "queue keys");
-  size_t tmp = c->sort_tmp_bytes;
-  e = hipcub::DeviceRadixSort::SortPairs(c->d_sort_tmp, tmp, c->d_keys, c->d_keys_sorted, c->d_vals, c->d_order,
-                                         a.n, 0, 64, s);
-  if (e != hipSuccess) return hip_fail(c, e, "queue sort");
-  e = lob::launch_queue_ranges(c->d_keys_sorted, a.n, c->d_range, c->d_queue, s);
-  if (e != hipSuccess) return hip_fail(c, e, "queue ranges");
-  a.queue = c->d_queue;
-  a.order = c->d_order;
-  a.bucket_range = c->d_range;
+  hipError_t e = lob::launch_process(a, g.spill, s);
+  return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+}
 
-  auto grid_for = [&](const Geometry &gg, int *blocks) -> lob_status {
-    int per_cu = 0;
-    hipError_t ee = lob::occupancy_persistent(gg.spill, gg.bpb * lob::kWave,
-                                              (size_t)gg.bpb * gg.per_wave * sizeof(int2), &per_cu);
-    if (ee != hipSuccess) return hip_fail(c, ee, "occupancy");
-    if (per_cu < 1) per_cu = 1;
-    if (p.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, p.waves_per_cu / gg.bpb));
-    *blocks = per_cu * c->num_cus;
-    return LOB_OK;
-  };
-
-  if (!split) {
-    a.bucket = 0;
-    int blocks = 0;
-    if ((st = grid_for(g, &blocks)) != LOB_OK) return st;
-    e = lob::launch_process(a, g.spill, true, blocks, s);
-    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "persistent launch");
-  }
-  // bucket 0: capacity <= W, fully LDS-resident; bucket 1: the rest, on a side
-  // stream with its own (larger) window, forked from and joined back into s
-  Geometry g0, g1;
-  if ((st = geometry(c, g.W, g.W, p.books_per_block, &g0)) != LOB_OK) return st;
-  const int big = std::max(p.lds_slots_big, g.W);
-  if ((st = geometry(c, big, c->max_cap, p.books_per_block, &g1)) != LOB_OK) return st;
-  int b0 = 0, b1 = 0;
-  if ((st = grid_for(g0, &b0)) != LOB_OK) return st;
-  if ((st = grid_for(g1, &b1)) != LOB_OK) return st;
-  if ((e = hipEventRecord(c->ev_fork, s)) != hipSuccess) return hip_fail(c, e, "fork");
-  if ((e = hipStreamWaitEvent(c->side_stream, c->ev_fork, 0)) != hipSuccess) return hip_fail(c, e, "fork");
-  lob::ProcArgs a1 = a;
-  a1.bucket = 1;
-  a1.W = g1.W;
-  a1.bpb = g1.bpb;
-  a1.lds_int2_per_wave = g1.per_wave;
-  e = lob::launch_process(a1, g1.spill, true, b1, c->side_stream);
-  if (e != hipSuccess) return hip_fail(c, e, "persistent launch (bucket 1)");
-  a.bucket = 0;
-  a.W = g0.W;
-  a.bpb = g0.bpb;
-  a.lds_int2_per_wave = g0.per_wave;
-  e = lob::launch_process(a, false, true, b0, s);
-  if (e != hipSuccess) return hip_fail(c, e, "persistent launch (bucket 0)");
-  if ((e = hipEventRecord(c->ev_join, c->side_stream)) != hipSuccess) return hip_fail(c, e, "join");
-  if ((e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess) return hip_fail(c, e, "join");
-  return LOB_OK;
+lob_status run_process(lob_ctx *c, const lob::ProcArgs &a, hipStream_t s) {
+  return launch(c, a, c->plan.lds_slots, c->max_cap, c->plan.books_per_block, s);
 }
 
 lob::ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n) {
@@ -289,21 +224,12 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
   auto alloc = [&](void **p, size_t bytes) {
     return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess;
   };
-  size_t sort_tmp = 0;
+  c->stage_bytes = sizeof(int32_t) * 2 * (size_t)c->n_books + sizeof(int64_t) * 2 * (size_t)c->n_books + 256;
   bool ok = alloc((void **)&c->d_hdr, sizeof(lob::BookHdr) * hdr.size()) &&
             alloc((void **)&c->d_books, sizeof(int2) * (size_t)book_int2) &&
             alloc((void **)&c->d_log, sizeof(int32_t) * lob::kTradeFields * (size_t)log_rec) &&
-            alloc((void **)&c->d_keys, sizeof(uint64_t) * c->n_books) &&
-            alloc((void **)&c->d_keys_sorted, sizeof(uint64_t) * c->n_books) &&
-            alloc((void **)&c->d_vals, sizeof(int32_t) * c->n_books) &&
-            alloc((void **)&c->d_order, sizeof(int32_t) * c->n_books) &&
-            alloc((void **)&c->d_range, sizeof(int32_t) * 4) && alloc((void **)&c->d_queue, sizeof(int32_t) * 4);
-  if (ok) {
-    ok = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, c->d_keys, c->d_keys_sorted, c->d_vals, c->d_order,
-                                            c->n_books, 0, 64) == hipSuccess &&
-         alloc(&c->d_sort_tmp, sort_tmp);
-    c->sort_tmp_bytes = std::max<size_t>(sort_tmp, 256);
-  }
+            alloc((void **)&c->d_stage, c->stage_bytes) &&
+            hipHostMalloc((void **)&c->h_stage, c->stage_bytes, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     g_create_error = "device allocation failed";
     free_ctx(c);
@@ -313,6 +239,8 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_ragged_done, hipEventDisableTiming);
   if (e == hipSuccess) (void)lob::set_process_lds_limit(c->max_lds);  // advisory on this platform
   if (e != hipSuccess) {
     g_create_error = std::string("context setup: ") + hipGetErrorString(e);
@@ -320,13 +248,14 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
     return LOB_EDEVICE;
   }
   // default plan: whole books in LDS when they fit comfortably, otherwise a
-  // 256-slot window with the rest in HBM; four books per workgroup
+  // 256-slot window with the rest in HBM; four books per workgroup; ragged calls
+  // in one launch, longest stream first
   c->plan.lds_slots = c->max_cap <= 1024 ? c->max_cap : 256;
   c->plan.books_per_block = 4;
-  c->plan.persistent = 0;
-  c->plan.waves_per_cu = 0;
-  c->plan.split_buckets = 0;
+  c->plan.ragged_split = 0;
   c->plan.lds_slots_big = c->max_cap;
+  c->plan.ragged_order = 1;
+  c->plan.books_per_block_big = 1;
   *out = c;
   return LOB_OK;
 }
@@ -349,16 +278,15 @@ lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan) {
   if (!ctx || !plan) return LOB_EINVAL;
   if (plan->lds_slots < 1 || plan->lds_slots > LOB_MAX_CAPACITY) return fail(ctx, LOB_EINVAL, "lds_slots");
   if (plan->books_per_block < 1 || plan->books_per_block > 16) return fail(ctx, LOB_EINVAL, "books_per_block");
-  if (plan->persistent != 0 && plan->persistent != 1) return fail(ctx, LOB_EINVAL, "persistent");
-  if (plan->waves_per_cu < 0) return fail(ctx, LOB_EINVAL, "waves_per_cu");
-  if (plan->split_buckets != 0 && plan->split_buckets != 1) return fail(ctx, LOB_EINVAL, "split_buckets");
-  if (plan->split_buckets && plan->lds_slots_big < plan->lds_slots)
-    return fail(ctx, LOB_EINVAL, "lds_slots_big < lds_slots");
-  const size_t need = (size_t)lds_int2_per_wave(std::min(plan->lds_slots, ctx->max_cap), ctx->L) * sizeof(int2);
-  if (need > ctx->max_lds) return fail(ctx, LOB_ECAP, "lds_slots does not fit in LDS");
-  if (plan->split_buckets &&
-      (size_t)lds_int2_per_wave(std::min(plan->lds_slots_big, ctx->max_cap), ctx->L) * sizeof(int2) > ctx->max_lds)
-    return fail(ctx, LOB_ECAP, "lds_slots_big does not fit in LDS");
+  if (plan->ragged_split < 0 || plan->ragged_split > LOB_MAX_CAPACITY) return fail(ctx, LOB_EINVAL, "ragged_split");
+  if (plan->lds_slots_big < 1 || plan->lds_slots_big > LOB_MAX_CAPACITY)
+    return fail(ctx, LOB_EINVAL, "lds_slots_big");
+  if (plan->ragged_order != 0 && plan->ragged_order != 1) return fail(ctx, LOB_EINVAL, "ragged_order");
+  if (plan->books_per_block_big < 1 || plan->books_per_block_big > 16)
+    return fail(ctx, LOB_EINVAL, "books_per_block_big");
+  for (int w : {plan->lds_slots, plan->lds_slots_big, plan->ragged_split > 0 ? plan->ragged_split : 1})
+    if ((size_t)lds_int2_per_wave(std::min(w, ctx->max_cap), ctx->L) * sizeof(int2) > ctx->max_lds)
+      return fail(ctx, LOB_ECAP, "LDS window does not fit in LDS");
   ctx->plan = *plan;
   return LOB_OK;
 }
@@ -387,6 +315,105 @@ lob_status lob_process_messages(lob_ctx *ctx, const int32_t *book_ids, int32_t n
   return run_process(ctx, a, (hipStream_t)stream);
 }
 
+lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books, const int32_t *msgs,
+                              const int64_t *msg_offsets_host, int32_t l2_mode, int32_t *l2_out, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (n_books == 0) return LOB_OK;
+  if (!msgs || !msg_offsets_host) return fail(ctx, LOB_EINVAL, "msgs / msg_offsets_host is NULL");
+  if (!aligned16(msgs)) return fail(ctx, LOB_EINVAL, "msgs must be 16-byte aligned");
+  if (l2_mode < LOB_L2_NONE || l2_mode > LOB_L2_FINAL) return fail(ctx, LOB_EINVAL, "l2_mode");
+  if (l2_mode != LOB_L2_NONE && !l2_out) return fail(ctx, LOB_EINVAL, "l2_out is NULL");
+  const lob_plan &p = ctx->plan;
+  // host-side schedule: validate ids, split into capacity buckets, order each bucket
+  std::vector<char> seen(ctx->n_books, 0);
+  std::vector<int32_t> small, big;
+  small.reserve(n_books);
+  for (int32_t i = 0; i < n_books; ++i) {
+    const int32_t b = book_ids_host ? book_ids_host[i] : i;
+    if (b < 0 || b >= ctx->n_books) return fail(ctx, LOB_EINVAL, "book id out of range");
+    if (seen[b]) return fail(ctx, LOB_EINVAL, "book id listed twice");
+    seen[b] = 1;
+    if (msg_offsets_host[i + 1] < msg_offsets_host[i]) return fail(ctx, LOB_EINVAL, "offsets decrease");
+    if (p.ragged_split > 0 && ctx->caps[b] > p.ragged_split)
+      big.push_back(i);
+    else
+      small.push_back(i);
+  }
+  auto len = [&](int32_t i) { return msg_offsets_host[i + 1] - msg_offsets_host[i]; };
+  if (p.ragged_order) {
+    auto longest_first = [&](int32_t x, int32_t y) { return len(x) != len(y) ? len(x) > len(y) : x < y; };
+    std::sort(small.begin(), small.end(), longest_first);
+    std::sort(big.begin(), big.end(), longest_first);
+  }
+  // stage [ids | rows | ranges] in pinned memory, one copy to the device
+  DeviceGuard g(ctx->device);
+  hipError_t e;
+  if (ctx->staged_pending) {
+    if ((e = hipEventSynchronize(ctx->ev_staged)) != hipSuccess) return hip_fail(ctx, e, "staging wait");
+    ctx->staged_pending = false;
+  }
+  int32_t *h_ids = ctx->h_stage;
+  int32_t *h_rows = h_ids + n_books;
+  int64_t *h_ranges = reinterpret_cast<int64_t *>(ctx->h_stage + 2 * (size_t)n_books);  // 8n bytes: aligned
+  int32_t k = 0;
+  for (const std::vector<int32_t> *v : {&small, &big})
+    for (int32_t i : *v) {
+      h_ids[k] = book_ids_host ? book_ids_host[i] : i;
+      h_rows[k] = i;
+      h_ranges[2 * k] = msg_offsets_host[i];
+      h_ranges[2 * k + 1] = msg_offsets_host[i + 1];
+      ++k;
+    }
+  const size_t bytes = reinterpret_cast<char *>(h_ranges + 2 * (size_t)n_books) - reinterpret_cast<char *>(h_ids);
+  hipStream_t s = (hipStream_t)stream;
+  // the device copy of the schedule is reused: wait for the kernels of the previous
+  // ragged call, whichever stream it was issued on
+  if (ctx->ragged_pending && (e = hipStreamWaitEvent(s, ctx->ev_ragged_done, 0)) != hipSuccess)
+    return hip_fail(ctx, e, "ragged order");
+  if ((e = hipMemcpyAsync(ctx->d_stage, ctx->h_stage, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(ctx, e, "staging copy");
+  if ((e = hipEventRecord(ctx->ev_staged, s)) != hipSuccess) return hip_fail(ctx, e, "staging event");
+  ctx->staged_pending = true;
+  const int32_t *d_ids = ctx->d_stage;
+  const int32_t *d_rows = d_ids + n_books;
+  const int64_t *d_ranges =
+      reinterpret_cast<const int64_t *>(ctx->d_stage + 2 * (size_t)n_books);
+  lob::ProcArgs a = base_args(ctx, d_ids, (int32_t)small.size());
+  a.msgs = msgs;
+  a.ranges = d_ranges;
+  a.out_rows = d_rows;
+  a.l2_mode = l2_mode;
+  a.l2_out = l2_out;
+  auto done = [&](lob_status r) -> lob_status {
+    if (r != LOB_OK) return r;
+    hipError_t ee = hipEventRecord(ctx->ev_ragged_done, s);
+    if (ee != hipSuccess) return hip_fail(ctx, ee, "ragged done event");
+    ctx->ragged_pending = true;
+    return LOB_OK;
+  };
+  if (big.empty())
+    return done(launch(ctx, a, p.ragged_split > 0 ? p.ragged_split : p.lds_slots,
+                       p.ragged_split > 0 ? std::min(p.ragged_split, ctx->max_cap) : ctx->max_cap,
+                       p.books_per_block, s));
+  // two buckets: the large-capacity launch on the side stream, forked from and
+  // joined back into the caller's stream
+  lob::ProcArgs b = a;
+  b.book_ids = d_ids + small.size();
+  b.out_rows = d_rows + small.size();
+  b.ranges = d_ranges + 2 * small.size();
+  b.n = (int32_t)big.size();
+  if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return hip_fail(ctx, e, "fork");
+  if ((e = hipStreamWaitEvent(ctx->side_stream, ctx->ev_fork, 0)) != hipSuccess) return hip_fail(ctx, e, "fork");
+  if ((st = launch(ctx, b, p.lds_slots_big, ctx->max_cap, p.books_per_block_big, ctx->side_stream)) != LOB_OK)
+    return st;
+  if ((st = launch(ctx, a, p.ragged_split, std::min(p.ragged_split, ctx->max_cap), p.books_per_block, s)) != LOB_OK)
+    return st;
+  if ((e = hipEventRecord(ctx->ev_join, ctx->side_stream)) != hipSuccess) return hip_fail(ctx, e, "join");
+  if ((e = hipStreamWaitEvent(s, ctx->ev_join, 0)) != hipSuccess) return hip_fail(ctx, e, "join");
+  return done(LOB_OK);
+}
+
 lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window, int32_t W,
                     const int32_t *actions, int32_t A, int32_t agent_tid, int32_t *l2_out, int32_t *agent_fills,
                     int32_t F, int32_t *agent_fill_counts, void *stream) {
@@ -411,12 +438,7 @@ lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, cons
   a.fill_cap = F;
   a.fill_counts = F > 0 ? agent_fill_counts : nullptr;
   a.agent_tid = agent_tid;
-  // a step never uses the persistent queue (keeps it capturable and cheap)
-  lob_plan saved = ctx->plan;
-  ctx->plan.persistent = 0;
-  st = run_process(ctx, a, (hipStream_t)stream);
-  ctx->plan = saved;
-  return st;
+  return run_process(ctx, a, (hipStream_t)stream);
 }
 
 lob_status lob_read_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *l2_out, void *stream) {

@@ -67,11 +67,10 @@ struct ProcArgs {
   int32_t W;           // LDS slots per side-pair array
   int32_t bpb;         // books (waves) per block
   int32_t lds_int2_per_wave;
-  // persistent mode
-  int32_t *queue;      // [2] counters (one per bucket queue) or nullptr
-  const int32_t *order;  // listed indices, longest stream first
-  const int32_t *bucket_range;  // device [3]: queue q covers order[range[q] .. range[q+1])
-  int32_t bucket;      // which queue this launch serves
+  // explicit per-book message ranges ([n][2] begin, end into msgs) and output rows
+  // (L2 / fills row of listed book i); nullptr = offs / identity
+  const int64_t *ranges;
+  const int32_t *out_rows;
 };
 
 }  // namespace lob

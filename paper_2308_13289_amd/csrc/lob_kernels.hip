@@ -24,6 +24,11 @@
 //
 // Books whose capacity exceeds the LDS window W keep slots >= W in their HBM
 // arrays (SPILL = true); the head of each side stays in LDS.
+//
+// Work distribution: one wave per listed book, workgroups dispatched in listed
+// order.  For ragged batches the host lists books longest stream first, so the
+// hardware workgroup dispatcher hands the next-longest book to whichever SIMD
+// frees up first (longest-processing-time-first list scheduling).
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <stdint.h>
@@ -408,7 +413,8 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
   st.log_cap = h->log_cap;
   st.log_count = h->log_count;
   st.log = a.log ? a.log + log_off * kTradeFields : nullptr;
-  st.fills = a.fills ? a.fills + (int64_t)i * a.fill_cap * kTradeFields : nullptr;
+  const int row = a.out_rows ? uni(a.out_rows[i]) : i;  // output row of this book
+  st.fills = a.fills ? a.fills + (int64_t)row * a.fill_cap * kTradeFields : nullptr;
   st.fill_cap = a.fill_cap;
   st.fill_count = 0;
   st.agent_tid = a.agent_tid;
@@ -429,7 +435,10 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
 
   if (a.msgs) {
     long long beg, end;
-    if (a.offs) {
+    if (a.ranges) {
+      beg = a.ranges[2 * i];
+      end = a.ranges[2 * i + 1];
+    } else if (a.offs) {
       beg = a.offs[i];
       end = a.offs[i + 1];
     } else {
@@ -442,7 +451,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
     const long long beg = (long long)i * a.w2;
     process_range(B, st, a, a.msgs2, beg, beg + a.w2, false, scratch);
   }
-  if (a.l2_mode == 2) write_l2(B, st, a.levels, a.l2_out + (int64_t)i * 4 * a.levels, scratch);
+  if (a.l2_mode == 2) write_l2(B, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels, scratch);
 
   // LDS window -> HBM
   for (int sd = 0; sd < 2; ++sd) {
@@ -453,7 +462,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
   }
   if (st.fills) {
     if (st.fill_count > st.fill_cap) st.flags |= kFlagFillsFull;
-    if (l == 0 && a.fill_counts) a.fill_counts[i] = st.fill_count;
+    if (l == 0 && a.fill_counts) a.fill_counts[row] = st.fill_count;
   }
   if (l == 0) {
     h->n[0] = st.n[0];
@@ -484,24 +493,6 @@ __global__ void __launch_bounds__(1024) k_process(ProcArgs a) {
   int2 *lds = smem + (int64_t)w * a.lds_int2_per_wave;
   int *scratch = reinterpret_cast<int *>(lds + 6 * a.W);
   run_book<SPILL>(a, i, lds, scratch);
-}
-
-// Persistent form: every wave takes listed books from a queue (longest stream
-// first) until the queue is empty.
-template <bool SPILL>
-__global__ void __launch_bounds__(1024) k_process_persistent(ProcArgs a) {
-  extern __shared__ int2 smem[];
-  const int w = threadIdx.x / kWave;
-  int2 *lds = smem + (int64_t)w * a.lds_int2_per_wave;
-  int *scratch = reinterpret_cast<int *>(lds + 6 * a.W);
-  const int qb = a.bucket_range[a.bucket], qe = a.bucket_range[a.bucket + 1];
-  for (;;) {
-    int t = 0;
-    if (lane_id() == 0) t = atomicAdd(a.queue + a.bucket, 1);
-    t = rdlane(t, 0) + qb;
-    if (t >= qe) break;
-    run_book<SPILL>(a, uni(a.order[t]), lds, scratch);
-  }
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -700,37 +691,6 @@ __global__ void __launch_bounds__(256) k_trade_copy(BookHdr *hdr, const int32_t 
   if (threadIdx.x == 0) h->log_count = 0;
 }
 
-// LPT queue: key = stream length of each listed book (for the persistent kernel);
-// bucket 0 = capacity <= W, bucket 1 = capacity > W (or everything in bucket 0).
-__global__ void k_queue_keys(const BookHdr *hdr, const int32_t *ids, int n, int n_total, const int64_t *offs,
-                             int w1, int W, int split, uint64_t *keys, int32_t *vals) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t len = offs ? offs[i + 1] - offs[i] : w1;
-  const int bid = ids ? ids[i] : i;
-  const int cap = (bid >= 0 && bid < n_total) ? hdr[bid].cap : 0;
-  const uint64_t bucket = (split && cap > W) ? 1 : 0;
-  // ascending sort: bucket first, then longer streams first
-  const uint64_t inv = (uint64_t)0x00FFFFFFFFFFFFFFull - (uint64_t)(len < 0 ? 0 : len);
-  keys[i] = (bucket << 56) | (inv & 0x00FFFFFFFFFFFFFFull);
-  vals[i] = i;
-}
-
-__global__ void k_queue_ranges(const uint64_t *keys_sorted, int n, int32_t *range, int32_t *queue) {
-  // one thread: range = {0, first index of bucket 1, n}; queue counters zeroed
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) / 2;
-    if ((keys_sorted[mid] >> 56) == 0) lo = mid + 1; else hi = mid;
-  }
-  range[0] = 0;
-  range[1] = lo;
-  range[2] = n;
-  queue[0] = 0;
-  queue[1] = 0;
-}
-
 __global__ void k_selftest(int32_t *out) {
   // lanes: scan of (lane % 7 + 1), ballot/mask checks
   const int l = lane_id();
@@ -744,41 +704,23 @@ __global__ void k_selftest(int32_t *out) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_process(const ProcArgs &a, bool spill, bool persistent, int blocks, hipStream_t s) {
+hipError_t launch_process(const ProcArgs &a, bool spill, hipStream_t s) {
   const int threads = a.bpb * kWave;
   const size_t lds = (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2);
-  if (persistent) {
-    if (spill)
-      hipLaunchKernelGGL(k_process_persistent<true>, dim3(blocks), dim3(threads), lds, s, a);
-    else
-      hipLaunchKernelGGL(k_process_persistent<false>, dim3(blocks), dim3(threads), lds, s, a);
-  } else {
-    const int grid = (a.n + a.bpb - 1) / a.bpb;
-    if (spill)
-      hipLaunchKernelGGL(k_process<true>, dim3(grid), dim3(threads), lds, s, a);
-    else
-      hipLaunchKernelGGL(k_process<false>, dim3(grid), dim3(threads), lds, s, a);
-  }
+  const int grid = (a.n + a.bpb - 1) / a.bpb;
+  if (spill)
+    hipLaunchKernelGGL(k_process<true>, dim3(grid), dim3(threads), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_process<false>, dim3(grid), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
 hipError_t set_process_lds_limit(size_t bytes) {
-  hipError_t e = hipSuccess;
-  e = hipFuncSetAttribute((const void *)k_process<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipError_t e = hipFuncSetAttribute((const void *)k_process<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_process<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_process_persistent<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_process_persistent<false>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-hipError_t occupancy_persistent(bool spill, int threads, size_t lds, int *blocks_per_cu) {
-  if (spill)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_process_persistent<true>, threads, lds);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_process_persistent<false>, threads, lds);
+  return hipFuncSetAttribute((const void *)k_process<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }
 
 hipError_t launch_reset(BookHdr *hdr, const int32_t *ids, int n, int n_total, hipStream_t s) {
@@ -820,19 +762,6 @@ hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *i
   if (e != hipSuccess || n == 0) return e;
   hipLaunchKernelGGL(k_trade_copy, dim3(n), dim3(256), 0, s, hdr, log, ids, n, n_total, counts, offsets,
                      max_records, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_queue_keys(const BookHdr *hdr, const int32_t *ids, int n, int n_total, const int64_t *offs,
-                             int w1, int W, int split, uint64_t *keys, int32_t *vals, hipStream_t s) {
-  hipLaunchKernelGGL(k_queue_keys, dim3((n + 255) / 256), dim3(256), 0, s, hdr, ids, n, n_total, offs, w1, W,
-                     split, keys, vals);
-  return hipGetLastError();
-}
-
-hipError_t launch_queue_ranges(const uint64_t *keys_sorted, int n, int32_t *range, int32_t *queue,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_queue_ranges, dim3(1), dim3(64), 0, s, keys_sorted, n, range, queue);
   return hipGetLastError();
 }
 

@@ -40,8 +40,8 @@ class Config(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     _fields_ = [("lds_slots", ctypes.c_int32), ("books_per_block", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("split_buckets", ctypes.c_int32), ("lds_slots_big", ctypes.c_int32),
+                ("ragged_split", ctypes.c_int32), ("lds_slots_big", ctypes.c_int32),
+                ("ragged_order", ctypes.c_int32), ("books_per_block_big", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
@@ -50,7 +50,7 @@ class Plan(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["lob_create", "lob_destroy", "lob_last_error", "lob_info", "lob_set_plan", "lob_get_plan",
-           "lob_process_messages", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
+           "lob_process_messages", "lob_process_ragged", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
            "lob_read_book", "lob_write_book", "lob_reset", "lob_selftest"]
 
 
@@ -78,6 +78,8 @@ def load(path=None):
     L.lob_get_plan.argtypes = [vp, ctypes.POINTER(Plan)]
     L.lob_process_messages.restype = i32
     L.lob_process_messages.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
+    L.lob_process_ragged.restype = i32
+    L.lob_process_ragged.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
     L.lob_step.restype = i32
     L.lob_step.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, i32, vp, vp]
     L.lob_read_l2.restype = i32
@@ -177,7 +179,10 @@ class Context:
 
     def set_plan(self, **kw):
         p = self.get_plan()
+        names = {f for f, _ in Plan._fields_}
         for k, v in kw.items():
+            if k not in names or k == "reserved":
+                raise KeyError(f"lob_plan has no field {k!r}")
             setattr(p, k, int(v))
         self._check(self._lib.lob_set_plan(self._h, ctypes.byref(p)))
         return p
@@ -188,6 +193,22 @@ class Context:
         self._check(self._lib.lob_process_messages(
             self._h, ids, n, _ptr(msgs, torch.int32, "msgs"), _ptr(offsets, torch.int64, "offsets"),
             l2_mode, _ptr(l2_out, torch.int32, "l2_out"), _stream(stream, self.device)))
+
+    def process_ragged(self, msgs, offsets_host, book_ids_host=None, l2_mode=L2_NONE, l2_out=None,
+                       stream=None):
+        """Ragged batch: offsets (and book ids) are host arrays; the library orders and
+        buckets the books (see lob_plan)."""
+        offs = np.ascontiguousarray(offsets_host, dtype=np.int64)
+        n = offs.shape[0] - 1
+        ids = None
+        if book_ids_host is not None:
+            ids = np.ascontiguousarray(book_ids_host, dtype=np.int32)
+            if ids.shape[0] != n:
+                raise ValueError("book_ids_host and offsets_host disagree")
+        self._check(self._lib.lob_process_ragged(
+            self._h, None if ids is None else ctypes.c_void_p(ids.ctypes.data), n,
+            _ptr(msgs, torch.int32, "msgs"), ctypes.c_void_p(offs.ctypes.data), l2_mode,
+            _ptr(l2_out, torch.int32, "l2_out"), _stream(stream, self.device)))
 
     def step(self, window, l2_out, actions=None, book_ids=None, agent_tid=-1, fills=None,
              fill_counts=None, stream=None):

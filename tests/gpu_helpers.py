@@ -33,7 +33,8 @@ def new_context(caps, levels=10, msgs_per_book=None, plan=None, log_room=None):
     return ctx
 
 
-def run_gpu(caps, msgs, offs, levels=10, l2_mode=lob.L2_NONE, plan=None, ctx=None, calls=1):
+def run_gpu(caps, msgs, offs, levels=10, l2_mode=lob.L2_NONE, plan=None, ctx=None, calls=1,
+            ragged=False):
     """Process every book's stream (optionally split into `calls` consecutive calls)
     and read back trades, L2, final books and counters."""
     caps = np.asarray(caps, np.int32)
@@ -61,7 +62,10 @@ def run_gpu(caps, msgs, offs, levels=10, l2_mode=lob.L2_NONE, plan=None, ctx=Non
         out = l2
         if l2_mode == lob.L2_PER_MESSAGE and calls > 1:
             out = torch.zeros((max(len(idx), 1), 2, levels, 2), dtype=torch.int32, device=dev())
-        ctx.process(d_sub, to_dev(sub_offs), l2_mode=mode, l2_out=out)
+        if ragged:
+            ctx.process_ragged(d_sub, sub_offs, l2_mode=mode, l2_out=out)
+        else:
+            ctx.process(d_sub, to_dev(sub_offs), l2_mode=mode, l2_out=out)
         if l2_mode == lob.L2_PER_MESSAGE and calls > 1 and len(idx):
             l2[torch.from_numpy(idx).to(dev())] = out[:len(idx)]
     torch.cuda.synchronize()

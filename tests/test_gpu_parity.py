@@ -23,6 +23,14 @@ from paper_2308_13289_amd import lob  # noqa: E402
 from paper_2308_13289_amd import workload as W  # noqa: E402
 from test_oracle_bruteforce import alphabet, to_msgs  # noqa: E402
 
+# The persistent work-queue kernel (device-side longest-first queue built with a
+# library radix sort, waves popping books with an atomic counter) faulted the GPU
+# on its first run and no defect in this project's code was found by reading it;
+# it was withdrawn and ragged batches use lob_process_ragged instead.  Its cases
+# stay here, skipped.
+WITHDRAWN = pytest.mark.skip(reason="persistent work-queue kernel withdrawn: its first GPU run "
+                                    "faulted and the cause was not found; see DESIGN.md")
+
 
 def test_selftest_primitives():
     out = lob.selftest().cpu().numpy()
@@ -76,9 +84,9 @@ def test_c0_full_parity_per_message_l2():
 @pytest.mark.parametrize("plan", [
     {"books_per_block": 1},
     {"books_per_block": 8},
-    {"persistent": 1},
+    pytest.param({"persistent": 1}, marks=WITHDRAWN),
     {"lds_slots": 64},                      # books past 64 orders spill to HBM
-    {"lds_slots": 64, "persistent": 1},
+    pytest.param({"lds_slots": 64, "persistent": 1}, marks=WITHDRAWN),
 ], ids=["bpb1", "bpb8", "persistent", "spill64", "spill64_persistent"])
 def test_plans_agree_c0(plan):
     w = W.c0()
@@ -90,9 +98,11 @@ def test_plans_agree_c0(plan):
 @pytest.mark.parametrize("plan", [
     {},
     {"lds_slots": 128},
-    {"persistent": 1},
-    {"persistent": 1, "lds_slots": 128, "split_buckets": 1, "lds_slots_big": 1000},
-    {"persistent": 1, "lds_slots": 128, "split_buckets": 1, "lds_slots_big": 256},
+    pytest.param({"persistent": 1}, marks=WITHDRAWN),
+    pytest.param({"persistent": 1, "lds_slots": 128, "split_buckets": 1, "lds_slots_big": 1000},
+                 marks=WITHDRAWN),
+    pytest.param({"persistent": 1, "lds_slots": 128, "split_buckets": 1, "lds_slots_big": 256},
+                 marks=WITHDRAWN),
 ], ids=["default", "spill128", "persistent", "split", "split_spill"])
 def test_ragged_mixed_capacities(plan):
     """Capacities {50,100,500,1000} and uneven stream lengths in one call."""
@@ -100,6 +110,42 @@ def test_ragged_mixed_capacities(plan):
     g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan)
     o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
     assert_same(g, o, f"ragged {plan}")
+
+
+@pytest.mark.parametrize("plan", [
+    {},
+    {"ragged_order": 0},
+    {"ragged_split": 100, "lds_slots_big": 1000},
+    {"ragged_split": 128, "lds_slots_big": 256, "books_per_block": 8, "books_per_block_big": 2},
+    {"ragged_split": 64, "lds_slots_big": 64, "lds_slots": 64},
+], ids=["lpt_one_launch", "listed_order", "split_lds", "split_spill", "split_small_windows"])
+def test_process_ragged(plan):
+    """lob_process_ragged: longest stream first, capacity buckets on two streams."""
+    w = W.ragged(n_books=96, max_flow=4000)
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan, ragged=True)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
+    assert_same(g, o, f"process_ragged {plan}")
+
+
+def test_process_ragged_ids_and_per_message_l2():
+    """Listed ids in a scrambled order, per-message L2, repeated and bad ids rejected."""
+    w = W.ragged(n_books=40, max_flow=1500)
+    ctx = new_context(w.caps, 10, np.diff(w.offs), plan={"ragged_split": 100, "lds_slots_big": 512})
+    perm = np.random.default_rng(3).permutation(w.n_books).astype(np.int32)
+    sel = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in perm])
+    soffs = np.concatenate([[0], np.cumsum(np.diff(w.offs)[perm])]).astype(np.int64)
+    l2 = torch.zeros((len(sel), 2, 10, 2), dtype=torch.int32, device="cuda:0")
+    ctx.process_ragged(to_dev(w.msgs[sel]), soffs, book_ids_host=perm, l2_mode=lob.L2_PER_MESSAGE,
+                       l2_out=l2)
+    o = run_oracle(w.caps[perm], w.msgs[sel], soffs, l2_mode=O.L2_PER_MESSAGE)
+    np.testing.assert_array_equal(l2.cpu().numpy(), o["l2"])
+    bad = perm.copy()
+    bad[1] = bad[0]
+    with pytest.raises(lob.LobError):
+        ctx.process_ragged(to_dev(w.msgs[sel]), soffs, book_ids_host=bad)
+    bad[1] = w.n_books
+    with pytest.raises(lob.LobError):
+        ctx.process_ragged(to_dev(w.msgs[sel]), soffs, book_ids_host=bad)
 
 
 def test_small_capacity_rejects_and_deep_books():
@@ -243,9 +289,19 @@ def test_reset_and_book_ids_subset():
     assert_same(g, o, "after reset")
 
 
+@WITHDRAWN
 def test_deterministic_repeat():
     w = W.ragged(n_books=64, max_flow=3000)
     a = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan={"persistent": 1})
     b = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan={"persistent": 1})
+    for k in ("trades", "trade_offs", "dumps", "l2"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_deterministic_repeat_ragged():
+    w = W.ragged(n_books=64, max_flow=3000)
+    plan = {"ragged_split": 100, "lds_slots_big": 256}
+    a = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan, ragged=True)
+    b = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan, ragged=True)
     for k in ("trades", "trade_offs", "dumps", "l2"):
         np.testing.assert_array_equal(a[k], b[k])
