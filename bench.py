@@ -167,12 +167,183 @@ def bench_uniform(args, w, desc):
     return res
 
 
+def verify_books(ctx, w, l2, ids):
+    """Bit-exact check of the listed books against the oracle (trades, final L2 and book)."""
+    from oracle import oracle as O
+    ids = np.asarray(ids, np.int32)
+    sel = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in ids])
+    soffs = np.concatenate([[0], np.cumsum(np.diff(w.offs)[ids])]).astype(np.int64)
+    o = O.run(w.caps[ids], w.msgs[sel], soffs, l2_mode=O.L2_FINAL, levels=LEVELS, dumps=True,
+              dump_cap=int(w.caps.max()), threads=host_cores())
+    d_ids = torch.from_numpy(ids).cuda()
+    st = ctx.read_status(d_ids)
+    total = int(st["log_records"].sum())
+    rec, _, toffs = ctx.read_trades(max(total, 1), book_ids=d_ids)
+    book = ctx.read_book(int(w.caps.max()), book_ids=d_ids)
+    torch.cuda.synchronize()
+    return bool(np.array_equal(toffs.cpu().numpy(), o["trade_offs"])
+                and np.array_equal(rec[:total].cpu().numpy(), o["trades"][:, :6])
+                and np.array_equal(l2.cpu().numpy()[ids], o["l2"])
+                and np.array_equal(book.cpu().numpy(), o["dumps"]))
+
+
+def bench_ragged(args, n_books=10_000, reps=3):
+    """Ragged batch: 10,000 books, capacity in {50,100,500,1000}, flow length
+    log-uniform in [1e2, 1e5]; one autotuned lob_process_ragged call against the
+    plain kernel run once per capacity bucket (lob_process_messages, whole books in
+    LDS, one launch after the other)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.perf_counter()
+    w = W.ragged(n_books=n_books, threads=host_cores())
+    log(f"ragged workload: {w.n_msgs} messages generated in {time.perf_counter() - t0:.1f}s")
+    lens = np.diff(w.offs)
+    ctx = lob.Context(w.caps, l2_levels=LEVELS, trade_log_records=w.caps.astype(np.int64) + 2 * lens)
+    d_msgs = torch.from_numpy(w.msgs).to(dev)
+    l2 = torch.zeros((n_books, 2, LEVELS, 2), dtype=torch.int32, device=dev)
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            ctx.reset(stream=stream)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts)), ts
+
+    # plain uniform-batch kernel, one launch per capacity bucket
+    buckets = []
+    for c in sorted(set(int(x) for x in w.caps)):
+        ids = np.nonzero(w.caps == c)[0].astype(np.int32)
+        idx = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in ids])
+        offs = np.concatenate([[0], np.cumsum(lens[ids])]).astype(np.int64)
+        buckets.append((c, torch.from_numpy(ids).to(dev), d_msgs[torch.from_numpy(idx).to(dev)],
+                        torch.from_numpy(offs).to(dev),
+                        torch.zeros((len(ids), 2, LEVELS, 2), dtype=torch.int32, device=dev)))
+
+    def plain():
+        for c, d_ids, d_bm, d_bo, bl2 in buckets:
+            ctx.set_plan(lds_slots=c, books_per_block=4)
+            ctx.process(d_bm, d_bo, book_ids=d_ids, l2_mode=lob.L2_FINAL, l2_out=bl2, stream=stream)
+
+    plain_ms, plain_all = timed(plain)
+    t1 = time.perf_counter()
+    plan, tuned_ms = ctx.autotune_ragged(d_msgs, w.offs, max_trials=args.tune_trials, stream=stream)
+    tune_s = time.perf_counter() - t1
+    ctx.set_plan(**plan)
+
+    def ragged():
+        ctx.process_ragged(d_msgs, w.offs, l2_mode=lob.L2_FINAL, l2_out=l2, stream=stream)
+
+    ragged_ms, ragged_all = timed(ragged)
+    # critical path: the longest stream alone
+    longest = int(np.argmax(lens))
+    one_offs = np.array([w.offs[longest], w.offs[longest + 1]], np.int64)
+    one_ms, _ = timed(lambda: ctx.process_ragged(d_msgs, one_offs, book_ids_host=np.array([longest], np.int32),
+                                                 stream=stream))
+    # bit-exact check after a full ragged run: the longest book and 15 random ones
+    ctx.reset(stream=stream)
+    ragged()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    check = np.unique(np.concatenate([[longest], rng.choice(n_books, 15, replace=False)])).astype(np.int32)
+    ok = verify_books(ctx, w, l2, check)
+    res = {"workload": f"{n_books} books, capacity {{50,100,500,1000}} (p .3/.4/.2/.1), flow log-uniform "
+                       f"1e2..1e5 (+cap initial orders), final L2",
+           "messages": w.n_msgs, "max_book_messages": int(lens.max()),
+           "ragged_msgs_per_s": w.n_msgs / (ragged_ms / 1e3), "ragged_ms": ragged_ms,
+           "plain_per_bucket_msgs_per_s": w.n_msgs / (plain_ms / 1e3), "plain_per_bucket_ms": plain_ms,
+           "ragged_over_plain": plain_ms / ragged_ms, "longest_book_alone_ms": one_ms,
+           "autotuned_plan": plan, "autotune_s": tune_s, "verified_books": len(check), "bit_exact": ok}
+    ctx.close()
+    return res
+
+
+def bench_step(args, n_books=8192, n_steps=1000, window=100, fills_cap=32):
+    """Environment-step form: 8192 books seeded with 50 orders per side, then
+    n_steps steps of (100-message data window + up to 4 agent orders) with the L2
+    snapshot and agent fills of every step; all windows and actions pre-staged in
+    HBM; the n_steps steps captured as one HIP graph."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.perf_counter()
+    w = W.step_workload(n_books=n_books, n_steps=n_steps, window=window, threads=host_cores())
+    seeds = w.extra["seed_msgs"]
+    log(f"step workload: {w.n_msgs} messages generated in {time.perf_counter() - t0:.1f}s")
+    ctx = lob.Context(w.caps, l2_levels=LEVELS, trade_log_records=w.caps.astype(np.int64))
+    per = seeds + n_steps * window
+    d_all = torch.from_numpy(w.msgs).to(dev).view(n_books, per, 8)
+    d_seed = d_all[:, :seeds].contiguous().view(-1, 8)
+    d_seed_offs = torch.arange(n_books + 1, dtype=torch.int64, device=dev) * seeds
+    d_win = d_all[:, seeds:].reshape(n_books, n_steps, window, 8).permute(1, 0, 2, 3).contiguous()
+    del d_all
+    d_act = torch.from_numpy(w.extra["actions"]).to(dev).permute(1, 0, 2, 3).contiguous()
+    n_act = int((w.extra["actions"][:, :, :, 0] != 0).sum())
+    del w
+    l2 = torch.zeros((n_steps, n_books, 2, LEVELS, 2), dtype=torch.int32, device=dev)
+    fills = torch.zeros((n_steps, n_books, fills_cap, 6), dtype=torch.int32, device=dev)
+    counts = torch.zeros((n_steps, n_books), dtype=torch.int32, device=dev)
+
+    def seed():
+        ctx.reset(stream=stream)
+        ctx.process(d_seed, d_seed_offs, stream=stream)
+
+    def one(s, st=stream):
+        # st=None: torch's current stream (the capture stream inside torch.cuda.graph)
+        ctx.step(d_win[s], l2[s], actions=d_act[s], agent_tid=-1, fills=fills[s], fill_counts=counts[s],
+                 stream=st)
+
+    # eager: per-step latency
+    seed()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
+    for s in range(n_steps):
+        ev[s][0].record(stream)
+        one(s)
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    eager_out = (l2[-1].clone(), counts.sum().item())
+    # graph: all steps captured once, replayed
+    seed()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for s in range(n_steps):
+            one(s, None)
+    reps = []
+    for _ in range(max(1, args.graph_reps)):
+        seed()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t1)
+    same = bool(torch.equal(l2[-1], eager_out[0]) and counts.sum().item() == eager_out[1])
+    total_msgs = n_books * n_steps * window + n_act
+    best = min(reps)
+    res = {"workload": f"{n_books} books x {n_steps} steps x ({window} data msgs + 0-4 agent orders), "
+                       f"capacity 100, L2 + agent fills per step, hipGraph of all steps",
+           "steps_per_s": n_steps / best, "msgs_per_s": total_msgs / best,
+           "graph_s": best, "graph_replays_s": reps,
+           "eager_step_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                             "mean": float(step_ms.mean()), "max": float(step_ms.max())},
+           "graph_equals_eager": same, "agent_fills": int(counts.sum().item())}
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c0"])
+    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3"])
+    ap.add_argument("--tune-trials", type=int, default=16)
+    ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -184,8 +355,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     lob.load()
+    if args.workload == "c3":
+        print(json.dumps(bench_step(args)), flush=True)
+        return
+    if args.workload == "c2":
+        print(json.dumps(bench_ragged(args)), flush=True)
+        return
     t0 = time.perf_counter()
-    if args.workload == "c1":
+    if args.workload in ("c1", "all"):
         w = W.c1(threads=host_cores())
         desc = "4096 books, capacity 100/side, 100 initial + 10000 flow messages each (41.4M msgs)"
     else:
@@ -197,6 +374,14 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, 1024)
         log(f"cpu baseline: {res['cpu_baseline']['value'] / 1e6:.2f} M msgs/s")
+    del w
+    if args.workload == "all":
+        res["ragged"] = bench_ragged(args)
+        log(f"ragged: {res['ragged']['ragged_msgs_per_s'] / 1e9:.3f} G msgs/s vs plain per bucket "
+            f"{res['ragged']['plain_per_bucket_msgs_per_s'] / 1e9:.3f}")
+        res["step_form"] = bench_step(args)
+        log(f"step form: {res['step_form']['steps_per_s']:.0f} steps/s, "
+            f"p99 {res['step_form']['eager_step_ms']['p99']:.3f} ms")
     print(json.dumps(res), flush=True)
 
 

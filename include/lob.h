@@ -185,6 +185,17 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
                               const int32_t *msgs, const int64_t *msg_offsets_host,
                               int32_t l2_mode, int32_t *l2_out, void *stream);
 
+/* Autotuner for lob_process_ragged: runs the batch under candidate plans -- one
+ * launch or two capacity buckets, LDS window sizes (books larger than the window
+ * keep their tail in HBM), books per workgroup -- times each run with HIP events
+ * on `stream`, installs the fastest plan in the context and returns it with its
+ * time.  Every run starts from empty books: the listed books are reset before each
+ * run and left reset at the end (their previous state is lost).  At most
+ * max_trials runs (>= 1).  Waits for the device (not graph-capturable). */
+lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books,
+                               const int32_t *msgs, const int64_t *msg_offsets_host,
+                               int32_t max_trials, lob_plan *best, float *best_ms, void *stream);
+
 /* One environment step per listed book (Section 5.1.3): the W data messages of
  * window[i] (zero padding skipped), then the A agent messages of actions[i]
  * (type 0 = no order), then the book's L2 snapshot into l2_out[i] and the trades

@@ -321,6 +321,7 @@ typedef struct {
   int32_t *l2_out;
   int32_t *trades;
   const int64_t *trade_offs;
+  int64_t *trade_msg;
   int64_t *trade_counts;
   orc_stats *stats;
   int32_t *dumps;
@@ -352,6 +353,7 @@ static int run_book(job_t *j, int32_t i) {
       if (tbase && stored < room) {
         memcpy(tbase + (size_t)stored * ORC_TRADE_FIELDS, scratch + (size_t)t * ORC_TRADE_FIELDS,
                sizeof(int32_t) * ORC_TRADE_FIELDS);
+        if (j->trade_msg) j->trade_msg[j->trade_offs[i] + stored] = k;
         stored++;
       } else if (tbase) {
         b->st.flags |= ORC_FLAG_TRADE_FULL;
@@ -403,8 +405,8 @@ static void *worker(void *arg) {
 
 int32_t orc_run(int32_t n_books, const int32_t *caps, const int32_t *msgs, const int64_t *offs,
                 int32_t l2_mode, int32_t levels, int32_t *l2_out, int32_t *trades,
-                const int64_t *trade_offs, int64_t *trade_counts, orc_stats *stats, int32_t *dumps,
-                int32_t dump_cap, int32_t n_threads) {
+                const int64_t *trade_offs, int64_t *trade_msg, int64_t *trade_counts,
+                orc_stats *stats, int32_t *dumps, int32_t dump_cap, int32_t n_threads) {
   if (n_books < 0 || !caps || !offs || (n_books > 0 && !msgs)) return -1;
   if (l2_mode != ORC_L2_NONE && (!l2_out || levels < 1)) return -1;
   if (dumps && dump_cap < 1) return -1;
@@ -421,6 +423,7 @@ int32_t orc_run(int32_t n_books, const int32_t *caps, const int32_t *msgs, const
   j.l2_out = l2_out;
   j.trades = trades;
   j.trade_offs = trade_offs;
+  j.trade_msg = trade_msg;
   j.trade_counts = trade_counts;
   j.stats = stats;
   j.dumps = dumps;

@@ -98,6 +98,8 @@ int32_t orc_capacity(const orc_book *b);
  *                            PER_MESSAGE and [n][2][levels][2] for FINAL
  *   trades, trade_offs[n+1]  book i may store trade_offs[i+1]-trade_offs[i]
  *                            records from trades + trade_offs[i]*8 (may be NULL)
+ *   trade_msg                NULL or int64 parallel to `trades`: index (into msgs)
+ *                            of the message that produced each stored trade
  *   trade_counts[n]          trades generated per book (may be NULL)
  *   stats[n]                 per-book counters (may be NULL)
  *   dumps                    NULL or [n][2][maxcap][6]: final books, {asks, bids}
@@ -105,8 +107,9 @@ int32_t orc_capacity(const orc_book *b);
  * Returns 0, or -1 on bad arguments / no memory. */
 int32_t orc_run(int32_t n_books, const int32_t *caps, const int32_t *msgs,
                 const int64_t *offs, int32_t l2_mode, int32_t levels, int32_t *l2_out,
-                int32_t *trades, const int64_t *trade_offs, int64_t *trade_counts,
-                orc_stats *stats, int32_t *dumps, int32_t dump_cap, int32_t n_threads);
+                int32_t *trades, const int64_t *trade_offs, int64_t *trade_msg,
+                int64_t *trade_counts, orc_stats *stats, int32_t *dumps, int32_t dump_cap,
+                int32_t n_threads);
 
 #ifdef __cplusplus
 }

@@ -69,7 +69,7 @@ def lib():
         L.orc_get_stats.argtypes = [VP, ctypes.POINTER(Stats)]
         L.orc_run.restype = ctypes.c_int32
         L.orc_run.argtypes = [ctypes.c_int32, P32, P32, P64, ctypes.c_int32, ctypes.c_int32, P32,
-                              P32, P64, P64, VP, P32, ctypes.c_int32, ctypes.c_int32]
+                              P32, P64, P64, P64, VP, P32, ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -131,7 +131,8 @@ def run(caps, msgs, offs, l2_mode=L2_NONE, levels=10, trade_room=None, dumps=Fal
 
     caps[n], msgs[total, 8] int32, offs[n+1] int64.  trade_room[n] = records kept
     per book (default: the bound 2 * messages).  Returns a dict with trades (8-field
-    records, concatenated per book), trade_offs, trade_counts, stats, l2, dumps."""
+    records, concatenated per book), trade_msg (message index of each trade),
+    trade_offs, trade_counts, stats, l2, dumps."""
     caps = np.ascontiguousarray(caps, dtype=np.int32)
     msgs = np.ascontiguousarray(msgs, dtype=np.int32).reshape(-1, 8)
     offs = np.ascontiguousarray(offs, dtype=np.int64)
@@ -143,6 +144,7 @@ def run(caps, msgs, offs, l2_mode=L2_NONE, levels=10, trade_room=None, dumps=Fal
     toffs = np.zeros(n + 1, np.int64)
     np.cumsum(trade_room, out=toffs[1:])
     trades = np.full((int(toffs[-1]), 8), -1, np.int32)
+    tmsg = np.full(int(toffs[-1]), -1, np.int64)
     counts = np.zeros(n, np.int64)
     stats = np.zeros(n, STATS_DTYPE)
     if l2_mode == L2_PER_MESSAGE:
@@ -155,8 +157,8 @@ def run(caps, msgs, offs, l2_mode=L2_NONE, levels=10, trade_room=None, dumps=Fal
     dump_arr = np.zeros((n, 2, dcap, 6), np.int32) if dumps else None
     nt = threads or os.cpu_count() or 1
     rc = lib().orc_run(n, _p32(caps), _p32(msgs), _p64(offs), l2_mode, levels, _p32(l2),
-                       _p32(trades), _p64(toffs), _p64(counts), stats.ctypes.data, _p32(dump_arr),
-                       dcap, nt)
+                       _p32(trades), _p64(toffs), _p64(tmsg), _p64(counts), stats.ctypes.data,
+                       _p32(dump_arr), dcap, nt)
     if rc != 0:
         raise RuntimeError("orc_run failed")
     kept = np.minimum(counts, trade_room)
@@ -165,5 +167,5 @@ def run(caps, msgs, offs, l2_mode=L2_NONE, levels=10, trade_room=None, dumps=Fal
         np.zeros(0, np.int64)
     koffs = np.zeros(n + 1, np.int64)
     np.cumsum(kept, out=koffs[1:])
-    return {"trades": trades[idx], "trade_offs": koffs, "trade_counts": counts, "stats": stats,
-            "l2": l2, "dumps": dump_arr}
+    return {"trades": trades[idx], "trade_msg": tmsg[idx], "trade_offs": koffs,
+            "trade_counts": counts, "stats": stats, "l2": l2, "dumps": dump_arr}

@@ -414,6 +414,120 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
   return done(LOB_OK);
 }
 
+lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books, const int32_t *msgs,
+                               const int64_t *msg_offsets_host, int32_t max_trials, lob_plan *best,
+                               float *best_ms, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (!best || max_trials < 1 || n_books < 1) return fail(ctx, LOB_EINVAL, "best / max_trials / n_books");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard g(ctx->device);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(ctx, LOB_EDEVICE, "autotune events");
+  const lob_plan base = ctx->plan;
+  // the listed books are the first n ints of the device schedule after a ragged
+  // call (in launch order), which is what the resets below use
+  auto reset_listed = [&]() -> lob_status {
+    hipError_t e = lob::launch_reset(ctx->d_hdr, ctx->d_stage, n_books, ctx->n_books, s);
+    return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "autotune reset");
+  };
+  int trials = 0;
+  float best_t = 1e30f;
+  lob_plan best_p = base;
+  auto trial = [&](lob_plan p) -> lob_status {
+    if (trials >= max_trials) return LOB_OK;
+    if (lob_set_plan(ctx, &p) != LOB_OK) return LOB_OK;  // candidate does not fit: skip it
+    ++trials;
+    lob_status r = lob_process_ragged(ctx, book_ids_host, n_books, msgs, msg_offsets_host, LOB_L2_NONE, nullptr,
+                                      stream);  // stages the schedule; warms caches
+    if (r != LOB_OK) return r;
+    if ((r = reset_listed()) != LOB_OK) return r;
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(ctx, LOB_EDEVICE, "autotune event");
+    r = lob_process_ragged(ctx, book_ids_host, n_books, msgs, msg_offsets_host, LOB_L2_NONE, nullptr, stream);
+    if (r != LOB_OK) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(ctx, LOB_EDEVICE, "autotune sync");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if ((r = reset_listed()) != LOB_OK) return r;
+    if (ms < best_t) {
+      best_t = ms;
+      best_p = p;
+    }
+    return LOB_OK;
+  };
+  // distinct capacities among the listed books (candidate bucket boundaries)
+  std::vector<int32_t> caps;
+  for (int32_t i = 0; i < n_books; ++i) {
+    const int32_t b = book_ids_host ? book_ids_host[i] : i;
+    if (b >= 0 && b < ctx->n_books) caps.push_back(ctx->caps[b]);
+  }
+  std::sort(caps.begin(), caps.end());
+  caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
+  const int maxc = caps.empty() ? ctx->max_cap : caps.back();
+  lob_status r = LOB_OK;
+  // stage 1: structure -- one launch with whole books in LDS or a small window,
+  // or two buckets split at each listed capacity below the largest
+  {
+    lob_plan p = base;
+    p.ragged_order = 1;
+    p.ragged_split = 0;
+    p.books_per_block = 4;
+    p.books_per_block_big = 1;
+    for (int w : {maxc, 128}) {
+      p.lds_slots = std::min(w, maxc);
+      if ((r = trial(p)) != LOB_OK) goto out;
+    }
+    for (size_t k = 0; k + 1 < caps.size(); ++k) {
+      p.lds_slots = std::min(128, maxc);
+      p.ragged_split = caps[k];
+      for (int wb : {maxc, 256}) {
+        p.lds_slots_big = std::min(wb, maxc);
+        if ((r = trial(p)) != LOB_OK) goto out;
+      }
+    }
+  }
+  // stage 2: books per workgroup of each launch
+  {
+    const lob_plan s1 = best_p;
+    for (int bpb : {1, 2, 8}) {
+      lob_plan p = s1;
+      p.books_per_block = bpb;
+      if ((r = trial(p)) != LOB_OK) goto out;
+    }
+    if (s1.ragged_split > 0)
+      for (int bb : {2, 4}) {
+        lob_plan p = best_p;
+        p.books_per_block_big = bb;
+        if ((r = trial(p)) != LOB_OK) goto out;
+      }
+  }
+  // stage 3: LDS window of the launch that can spill
+  {
+    const lob_plan s2 = best_p;
+    for (int w : {64, 256, 512}) {
+      lob_plan p = s2;
+      if (p.ragged_split > 0)
+        p.lds_slots_big = std::min(w, maxc);
+      else
+        p.lds_slots = std::min(w, maxc);
+      if ((r = trial(p)) != LOB_OK) goto out;
+    }
+  }
+out:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r != LOB_OK) {
+    ctx->plan = base;
+    return r;
+  }
+  ctx->plan = best_p;
+  *best = best_p;
+  if (best_ms) *best_ms = best_t;
+  return LOB_OK;
+}
+
 lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window, int32_t W,
                     const int32_t *actions, int32_t A, int32_t agent_tid, int32_t *l2_out, int32_t *agent_fills,
                     int32_t F, int32_t *agent_fill_counts, void *stream) {

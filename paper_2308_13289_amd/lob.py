@@ -50,7 +50,7 @@ class Plan(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["lob_create", "lob_destroy", "lob_last_error", "lob_info", "lob_set_plan", "lob_get_plan",
-           "lob_process_messages", "lob_process_ragged", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
+           "lob_process_messages", "lob_process_ragged", "lob_autotune_ragged", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
            "lob_read_book", "lob_write_book", "lob_reset", "lob_selftest"]
 
 
@@ -80,6 +80,9 @@ def load(path=None):
     L.lob_process_messages.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
     L.lob_process_ragged.restype = i32
     L.lob_process_ragged.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
+    L.lob_autotune_ragged.restype = i32
+    L.lob_autotune_ragged.argtypes = [vp, vp, i32, vp, vp, i32, ctypes.POINTER(Plan),
+                                      ctypes.POINTER(ctypes.c_float), vp]
     L.lob_step.restype = i32
     L.lob_step.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, i32, vp, vp]
     L.lob_read_l2.restype = i32
@@ -209,6 +212,20 @@ class Context:
             self._h, None if ids is None else ctypes.c_void_p(ids.ctypes.data), n,
             _ptr(msgs, torch.int32, "msgs"), ctypes.c_void_p(offs.ctypes.data), l2_mode,
             _ptr(l2_out, torch.int32, "l2_out"), _stream(stream, self.device)))
+
+    def autotune_ragged(self, msgs, offsets_host, book_ids_host=None, max_trials=24, stream=None):
+        """Pick (and install) the fastest plan for this ragged batch; resets the
+        listed books.  Returns (plan dict, best time in ms)."""
+        offs = np.ascontiguousarray(offsets_host, dtype=np.int64)
+        n = offs.shape[0] - 1
+        ids = None if book_ids_host is None else np.ascontiguousarray(book_ids_host, dtype=np.int32)
+        best = Plan()
+        ms = ctypes.c_float()
+        self._check(self._lib.lob_autotune_ragged(
+            self._h, None if ids is None else ctypes.c_void_p(ids.ctypes.data), n,
+            _ptr(msgs, torch.int32, "msgs"), ctypes.c_void_p(offs.ctypes.data), int(max_trials),
+            ctypes.byref(best), ctypes.byref(ms), _stream(stream, self.device)))
+        return best.as_dict(), float(ms.value)
 
     def step(self, window, l2_out, actions=None, book_ids=None, agent_tid=-1, fills=None,
              fill_counts=None, stream=None):

@@ -305,3 +305,17 @@ def test_deterministic_repeat_ragged():
     b = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan, ragged=True)
     for k in ("trades", "trade_offs", "dumps", "l2"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_autotune_ragged_keeps_results_exact():
+    """The autotuner only changes speed: after it installs its plan, a ragged run is
+    still bit-exact, and the tuned books start from empty."""
+    w = W.ragged(n_books=64, max_flow=3000)
+    ctx = new_context(w.caps, 10, np.diff(w.offs))
+    plan, ms = ctx.autotune_ragged(to_dev(w.msgs), w.offs, max_trials=8)
+    assert ms > 0 and plan["books_per_block"] >= 1
+    st = ctx.read_status()
+    assert (st["n_msgs"] == 0).all() and (st["log_records"] == 0).all()
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, ctx=ctx, ragged=True)
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
+    assert_same(g, o, f"after autotune {plan}")

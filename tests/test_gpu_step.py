@@ -1,0 +1,180 @@
+"""Environment-step form (lob_step) against the oracle, eager and as a captured
+HIP graph.
+
+One step of a book = its 100-message data window, then up to 4 agent orders
+(trader id -1), then its L2 snapshot and the step's agent fills (Section 5.1.3:
+actions become messages, the data window is fetched, everything is processed).
+The oracle sees each book as one stream: initial orders, then window + agent
+orders of every step; the snapshot after a step is the per-message L2 row of the
+step's last message, and the agent fills are the trades produced by the step's
+messages in which either side carries trader id -1.
+"""
+import numpy as np
+import pytest
+import torch
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_helpers import to_dev  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+from paper_2308_13289_amd import lob  # noqa: E402
+from paper_2308_13289_amd import workload as W  # noqa: E402
+
+AGENT = -1
+
+
+def step_case(n_books, n_steps, window=100, cap=100):
+    w = W.step_workload(n_books=n_books, n_steps=n_steps, window=window, cap=cap)
+    seeds = w.extra["seed_msgs"]
+    allm = w.msgs.reshape(n_books, seeds + n_steps * window, 8)
+    seed_blk = np.ascontiguousarray(allm[:, :seeds])
+    windows = np.ascontiguousarray(allm[:, seeds:].reshape(n_books, n_steps, window, 8))
+    actions = w.extra["actions"]
+    return w, seed_blk, windows, actions
+
+
+def oracle_steps(caps, seed_blk, windows, actions, levels=10):
+    """Per-step L2 [steps][n][2][L][2], agent fills (list per step per book) from
+    the oracle run over each book's concatenated stream."""
+    n, steps = windows.shape[0], windows.shape[1]
+    streams, ends = [], np.zeros((n, steps), np.int64)
+    begs = np.zeros((n, steps), np.int64)
+    pos = 0
+    for b in range(n):
+        parts = [seed_blk[b]]
+        pos += len(seed_blk[b])
+        for s in range(steps):
+            act = actions[b, s][actions[b, s, :, 0] != 0]
+            begs[b, s] = pos
+            parts += [windows[b, s], act]
+            pos += len(windows[b, s]) + len(act)
+            ends[b, s] = pos - 1
+        streams.append(np.concatenate(parts))
+    msgs = np.concatenate(streams)
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in streams])]).astype(np.int64)
+    r = O.run(caps, msgs, offs, l2_mode=O.L2_PER_MESSAGE, levels=levels)
+    l2 = r["l2"][ends.T]  # [steps][n][2][L][2]
+    fills = [[None] * n for _ in range(steps)]
+    for b in range(n):
+        tr = r["trades"][r["trade_offs"][b]:r["trade_offs"][b + 1]]
+        tm = r["trade_msg"][r["trade_offs"][b]:r["trade_offs"][b + 1]]
+        ag = (tr[:, 6] == AGENT) | (tr[:, 7] == AGENT)
+        for s in range(steps):
+            sel = ag & (tm >= begs[b, s]) & (tm <= ends[b, s])
+            fills[s][b] = tr[sel, :6]
+    return l2, fills
+
+
+class StepRunner:
+    def __init__(self, caps, seed_blk, windows, actions, F=64, levels=10):
+        self.n, self.steps = windows.shape[0], windows.shape[1]
+        self.ctx = lob.Context(caps, l2_levels=levels, trade_log_records=np.asarray(caps, np.int64) * 2)
+        self.seed_msgs = to_dev(seed_blk.reshape(-1, 8))
+        self.seed_offs = to_dev(np.arange(self.n + 1, dtype=np.int64) * seed_blk.shape[1])
+        self.win = [to_dev(windows[:, s]) for s in range(self.steps)]
+        self.act = [to_dev(actions[:, s]) for s in range(self.steps)]
+        dev = torch.device("cuda:0")
+        self.l2 = torch.zeros((self.steps, self.n, 2, levels, 2), dtype=torch.int32, device=dev)
+        self.fills = torch.zeros((self.steps, self.n, F, 6), dtype=torch.int32, device=dev)
+        self.counts = torch.zeros((self.steps, self.n), dtype=torch.int32, device=dev)
+
+    def seed(self):
+        self.ctx.reset()
+        self.ctx.process(self.seed_msgs, self.seed_offs)
+
+    def run_steps(self):
+        for s in range(self.steps):
+            self.ctx.step(self.win[s], self.l2[s], actions=self.act[s], agent_tid=AGENT,
+                          fills=self.fills[s], fill_counts=self.counts[s])
+
+    def outputs(self):
+        torch.cuda.synchronize()
+        return self.l2.cpu().numpy().copy(), self.fills.cpu().numpy().copy(), self.counts.cpu().numpy().copy()
+
+
+def check_against_oracle(l2, fills, counts, ol2, ofills, F):
+    np.testing.assert_array_equal(l2, ol2)
+    for s in range(len(ofills)):
+        for b in range(len(ofills[s])):
+            want = ofills[s][b]
+            assert counts[s, b] == len(want), (s, b)
+            k = min(F, len(want))
+            np.testing.assert_array_equal(fills[s, b, :k], want[:k], err_msg=f"step {s} book {b}")
+
+
+def test_step_eager_matches_oracle():
+    w, seed_blk, windows, actions = step_case(48, 25)
+    F = 64
+    R = StepRunner(w.caps, seed_blk, windows, actions, F=F)
+    R.seed()
+    R.run_steps()
+    l2, fills, counts = R.outputs()
+    ol2, ofills = oracle_steps(w.caps, seed_blk, windows, actions)
+    assert sum(len(f) for st in ofills for f in st) > 100  # the agent does trade
+    check_against_oracle(l2, fills, counts, ol2, ofills, F)
+    st = R.ctx.read_status()
+    assert (st["log_records"] == 0).all()  # steps do not log trades
+
+
+def test_step_fills_overflow_flagged():
+    w, seed_blk, windows, actions = step_case(16, 10)
+    F = 1
+    R = StepRunner(w.caps, seed_blk, windows, actions, F=F)
+    R.seed()
+    R.run_steps()
+    l2, fills, counts = R.outputs()
+    ol2, ofills = oracle_steps(w.caps, seed_blk, windows, actions)
+    check_against_oracle(l2, fills, counts, ol2, ofills, F)
+    st = R.ctx.read_status()
+    many = np.array([max(len(ofills[s][b]) for s in range(10)) > 1 for b in range(16)])
+    assert many.any()
+    np.testing.assert_array_equal((st["flags"] & lob.BOOK_FILLS_FULL) != 0, many)
+
+
+def test_step_graph_replays_match_eager():
+    """Capture all steps in one graph; restore the seeded books eagerly between
+    replays; every replay must equal the eager run and the oracle."""
+    w, seed_blk, windows, actions = step_case(32, 12)
+    F = 64
+    R = StepRunner(w.caps, seed_blk, windows, actions, F=F)
+    R.seed()
+    R.run_steps()
+    eager = R.outputs()
+    ol2, ofills = oracle_steps(w.caps, seed_blk, windows, actions)
+    check_against_oracle(*eager, ol2, ofills, F)
+    R.seed()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        R.run_steps()
+    for rep in range(3):
+        R.seed()                     # eager work between replays
+        R.l2.zero_()
+        R.fills.zero_()
+        R.counts.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        got = R.outputs()
+        for a, b in zip(got, eager):
+            np.testing.assert_array_equal(a, b, err_msg=f"replay {rep}")
+
+
+def test_step_window_padding_and_no_actions():
+    """Zero-padded window rows are skipped; steps without actions (A = 0)."""
+    w, seed_blk, windows, actions = step_case(8, 6)
+    windows = windows.copy()
+    windows[:, 3, 50:] = 0                       # a half-padded window
+    no_act = np.zeros_like(actions)
+    ctx = lob.Context(w.caps, l2_levels=10, trade_log_records=np.asarray(w.caps, np.int64) * 2)
+    ctx.process(to_dev(seed_blk.reshape(-1, 8)), to_dev(np.arange(9, dtype=np.int64) * seed_blk.shape[1]))
+    l2 = torch.zeros((6, 8, 2, 10, 2), dtype=torch.int32, device="cuda:0")
+    for s in range(6):
+        ctx.step(to_dev(windows[:, s]), l2[s])
+    torch.cuda.synchronize()
+    ol2, _ = oracle_steps(w.caps, seed_blk, windows, no_act)
+    np.testing.assert_array_equal(l2.cpu().numpy(), ol2)
