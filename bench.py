@@ -262,6 +262,74 @@ def bench_ragged(args, n_books=10_000, reps=3):
     return res
 
 
+def bench_serving(args, n_books=20_000, lams=(50_000, 100_000, 200_000, 500_000), duration_s=0.5):
+    """Serving loop: 20,000 books of capacity {50,100,500,1000} resident in HBM;
+    replay and step requests (1..1000 messages, log-uniform; steps add up to 4
+    agent orders) arrive as a Poisson process; the native server batches them
+    continuously under a 1 GiB staging budget.  Latency = host-visible completion
+    minus arrival.  A sample of books is checked bit-exact against the oracle
+    replayed in arrival order."""
+    from paper_2308_13289_amd import serve as S
+    from oracle import oracle as O
+    dev = torch.device("cuda:0")
+    out = {"workload": f"{n_books} books, capacity {{50,100,500,1000}}, Poisson arrivals for "
+                       f"{duration_s}s per rate, 50% replay / 50% step, 1..1000 msgs per request, "
+                       f"4 batch slots, 1 GiB staging budget", "rates": []}
+    for lam in lams:
+        t0 = time.perf_counter()
+        sw = S.ServingWorkload(n_books, lam, duration_s, threads=host_cores())
+        caps = sw.caps
+        ctx = lob.Context(caps, l2_levels=LEVELS, trade_log_records=2 * caps.astype(np.int64) + 2 * 1004)
+        ctx.set_plan(lds_slots=128, books_per_block=2)
+        s0, s1 = sw.seed_offsets
+        seeds = np.concatenate([sw.w.msgs[a:b] for a, b in zip(s0, s1)])
+        soffs = np.concatenate([[0], np.cumsum(s1 - s0)]).astype(np.int64)
+        ctx.process(torch.from_numpy(seeds).to(dev), torch.from_numpy(soffs).to(dev))
+        torch.cuda.synchronize()
+        reqs = sw.requests()
+        log(f"serving {lam / 1e3:.0f}k req/s: {sw.n} requests, {int(sw.size.sum())} msgs prepared in "
+            f"{time.perf_counter() - t0:.1f}s")
+        srv = S.Server(ctx, n_slots=4, hbm_budget=1 << 30, max_batch=4096, max_request_msgs=1000, fill_cap=64)
+        comp = srv.run(reqs, sw.arrival)
+        srv.close()
+        lat = (comp["complete_ns"] - comp["arrival_ns"]) / 1e6
+        kinds = sw.kind[comp["tag"]]
+        span_s = (comp["complete_ns"].max() - comp["arrival_ns"].min()) / 1e9
+        msgs = int(sw.size.sum() + sw.n_actions.sum())
+        # bit-exact check of 24 books' requests against the oracle in arrival order
+        rng = np.random.default_rng(int(lam))
+        books = sorted(rng.choice(n_books, 24, replace=False).tolist())
+        m, o_offs, spans = sw.oracle_streams(books)
+        r = O.run(caps[np.asarray(books)], m, o_offs, l2_mode=O.L2_PER_MESSAGE, levels=LEVELS,
+                  threads=host_cores())
+        n_out = dict(zip(comp["tag"], comp["n_out"]))
+        ok = bool((comp["status"] == lob.OK).all())
+        for k, first, last in spans:
+            sel = (r["trade_msg"] >= first) & (r["trade_msg"] <= last)
+            if sw.kind[k] == S.REPLAY:
+                got = sw.trades[sw.trade_offs[k]:sw.trade_offs[k] + n_out[k]]
+                ok &= np.array_equal(got, r["trades"][sel, :6])
+            else:
+                ag = sel & ((r["trades"][:, 6] == -1) | (r["trades"][:, 7] == -1))
+                ok &= np.array_equal(sw.l2[k], r["l2"][last]) and \
+                    np.array_equal(sw.fills[k][:n_out[k]], r["trades"][ag, :6])
+        out["rates"].append({
+            "offered_req_per_s": lam, "requests": int(sw.n), "messages": msgs,
+            "msgs_per_s": msgs / span_s, "req_per_s": sw.n / span_s,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "step_latency_ms": {"p50": float(np.percentile(lat[kinds == S.STEP], 50)),
+                                "p99": float(np.percentile(lat[kinds == S.STEP], 99))},
+            "replay_latency_ms": {"p50": float(np.percentile(lat[kinds == S.REPLAY], 50)),
+                                  "p99": float(np.percentile(lat[kinds == S.REPLAY], 99))},
+            "checked_books": len(books), "checked_requests": len(spans), "bit_exact": bool(ok)})
+        log(f"  p50 {out['rates'][-1]['latency_ms']['p50']:.3f} ms, p99 {out['rates'][-1]['latency_ms']['p99']:.3f} ms, "
+            f"{out['rates'][-1]['msgs_per_s'] / 1e6:.1f} M msgs/s, exact={ok}")
+        ctx.close()
+        del sw, reqs, comp
+    return out
+
+
 def bench_step(args, n_books=8192, n_steps=1000, window=100, fills_cap=32):
     """Environment-step form: 8192 books seeded with 50 orders per side, then
     n_steps steps of (100-message data window + up to 4 agent orders) with the L2
@@ -341,7 +409,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3"])
+    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3", "c4"])
     ap.add_argument("--tune-trials", type=int, default=16)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
@@ -360,6 +428,9 @@ def main():
         return
     if args.workload == "c2":
         print(json.dumps(bench_ragged(args)), flush=True)
+        return
+    if args.workload == "c4":
+        print(json.dumps(bench_serving(args)), flush=True)
         return
     t0 = time.perf_counter()
     if args.workload in ("c1", "all"):
@@ -382,6 +453,7 @@ def main():
         res["step_form"] = bench_step(args)
         log(f"step form: {res['step_form']['steps_per_s']:.0f} steps/s, "
             f"p99 {res['step_form']['eager_step_ms']['p99']:.3f} ms")
+        res["serving"] = bench_serving(args)
     print(json.dumps(res), flush=True)
 
 

@@ -250,6 +250,74 @@ lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, voi
  * lanes <= lane with lane % 3 == 0, [128,192) number of lanes below lane. */
 lob_status lob_selftest(int32_t device, int32_t *out, void *stream);
 
+/* ---------------------------------------------------------------- serving */
+
+/* A request loop over the books of one context: requests arrive one by one, each
+ * for one book -- a replay request (messages; returns the trades they make) or a
+ * step request (messages, then up to 4 agent orders; returns the book's L2 and
+ * the step's agent fills).  The server keeps at most one request per book on the
+ * device, so every book sees its requests in arrival order; it gathers whatever
+ * has arrived into a batch whenever a batch slot (stream) is free and the batch
+ * fits the slot's share of the HBM staging budget, so batches run while new ones
+ * are formed.  Book state stays resident in the context between requests. */
+#define LOB_REQ_REPLAY 0
+#define LOB_REQ_STEP 1
+
+typedef struct {
+  int32_t n_slots;        /* batches in flight at once, each on its own stream, 1..16 */
+  int64_t hbm_budget;     /* bytes of device staging shared by the slots (inputs,
+                             outputs, trades room); a request waits until it fits */
+  int32_t max_batch;      /* requests per batch, >= 1                              */
+  int32_t max_request_msgs; /* largest request accepted (messages)                 */
+  int32_t fill_cap;       /* agent fills kept per step request on the device        */
+  int32_t agent_tid;      /* trader id that marks the agent's orders                */
+} lob_server_config;
+
+typedef struct {
+  int64_t tag;                 /* caller's id, echoed in the completion             */
+  int32_t book;                /* book id in the context                            */
+  int32_t kind;                /* LOB_REQ_REPLAY or LOB_REQ_STEP                    */
+  const int32_t *msgs_host;    /* [n_msgs][8] message records                       */
+  int32_t n_msgs;              /* 0..max_request_msgs                               */
+  int32_t n_actions;           /* step: agent messages in actions_host, 0..4        */
+  const int32_t *actions_host; /* [n_actions][8]                                    */
+  int32_t *trades_host;        /* replay: room for trades_room trade records        */
+  int32_t trades_room;
+  int32_t *l2_host;            /* step: [2][levels][2]                              */
+  int32_t *fills_host;         /* step: room for fills_room trade records           */
+  int32_t fills_room;
+} lob_request;
+/* All host buffers of a request must stay valid until its completion is returned. */
+
+typedef struct {
+  int64_t tag;
+  int32_t status;       /* LOB_OK, or LOB_ECAP when the trades / fills did not all fit
+                           (the caller's room or fill_cap); n_out is still exact      */
+  int32_t n_out;        /* trades (replay) or agent fills (step) the request made    */
+  int64_t arrival_ns;   /* server clock (lob_server_now) at arrival                  */
+  int64_t launch_ns;    /* when its batch was handed to the GPU                      */
+  int64_t complete_ns;  /* when its results were in the caller's host buffers        */
+} lob_completion;
+
+typedef struct lob_server lob_server;
+
+/* Allocates every staging buffer the server uses (device and pinned host). */
+lob_status lob_server_create(lob_ctx *ctx, const lob_server_config *cfg, lob_server **out);
+/* Waits for the batches in flight, then frees the server (not the context). */
+void lob_server_destroy(lob_server *srv);
+/* Nanoseconds on the server's clock (steady, since creation). */
+int64_t lob_server_now(const lob_server *srv);
+/* Queue a request that arrived at arrival_ns (server clock); no GPU work. */
+lob_status lob_server_submit(lob_server *srv, const lob_request *req, int64_t arrival_ns);
+/* Advance: retire finished batches (results copied to the requests' buffers),
+ * launch new batches from the queue; up to max_out completions into out. */
+lob_status lob_server_poll(lob_server *srv, lob_completion *out, int32_t max_out, int32_t *n_out);
+/* Open-loop driver: request k arrives arrival_ns[k] after the call starts
+ * (non-decreasing); submits each at its time and polls until all n have
+ * completed; completions go to out[0..n) in completion order. */
+lob_status lob_server_run(lob_server *srv, const lob_request *reqs, const int64_t *arrival_ns, int64_t n,
+                          lob_completion *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,47 +11,7 @@
 #include "lob.h"
 #include "lob_internal.h"
 
-namespace lob {
-hipError_t launch_process(const ProcArgs &a, bool spill, hipStream_t s);
-hipError_t set_process_lds_limit(size_t bytes);
-hipError_t launch_reset(BookHdr *hdr, const int32_t *ids, int n, int n_total, hipStream_t s);
-hipError_t launch_status(const BookHdr *hdr, const int32_t *ids, int n, int n_total, void *out, hipStream_t s);
-hipError_t launch_read_l2(const BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
-                          int32_t *out, hipStream_t s);
-hipError_t launch_read_book(const BookHdr *hdr, const int2 *books, const int32_t *ids, int n, int n_total,
-                            int dump_cap, int32_t *out, hipStream_t s);
-hipError_t launch_write_book(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int dump_cap,
-                             const int32_t *in, hipStream_t s);
-hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *ids, int n, int n_total,
-                              int32_t *out, int64_t max_records, int64_t *counts, int64_t *offsets,
-                              hipStream_t s);
-hipError_t launch_selftest(int32_t *out, hipStream_t s);
-}  // namespace lob
-
-static_assert(sizeof(lob_book_status) == 96, "lob_book_status layout");
-
-struct lob_ctx {
-  int device = 0;
-  int n_books = 0, L = 10, max_cap = 0;
-  std::vector<int32_t> caps;
-  lob::BookHdr *d_hdr = nullptr;
-  int2 *d_books = nullptr;
-  int32_t *d_log = nullptr;
-  lob_plan plan{};
-  std::string err;
-  int num_cus = 0;
-  size_t max_lds = 0;
-  // ragged schedule: listed ids, message ranges and output rows of one call, staged
-  // in pinned host memory and copied to the device in one transfer
-  int32_t *h_stage = nullptr, *d_stage = nullptr;
-  size_t stage_bytes = 0;
-  hipEvent_t ev_staged = nullptr;  // the last staging copy has completed
-  bool staged_pending = false;
-  hipEvent_t ev_ragged_done = nullptr;  // all work of the last ragged call
-  bool ragged_pending = false;
-  hipStream_t side_stream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-};
+#include "lob_ctx.h"
 
 namespace {
 
@@ -147,8 +107,12 @@ lob_status run_process(lob_ctx *c, const lob::ProcArgs &a, hipStream_t s) {
   return launch(c, a, c->plan.lds_slots, c->max_cap, c->plan.books_per_block, s);
 }
 
-lob::ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n) {
-  lob::ProcArgs a;
+
+}  // namespace
+
+namespace lob {
+ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n) {
+  ProcArgs a;
   std::memset(&a, 0, sizeof(a));
   a.hdr = c->d_hdr;
   a.books = c->d_books;
@@ -159,8 +123,9 @@ lob::ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n) {
   a.levels = c->L;
   return a;
 }
-
-}  // namespace
+lob_status launch_with_plan(lob_ctx *c, const ProcArgs &a, hipStream_t s) { return run_process(c, a, s); }
+lob_status set_error(lob_ctx *c, lob_status st, const std::string &msg) { return fail(c, st, msg); }
+}  // namespace lob
 
 extern "C" {
 
@@ -307,7 +272,7 @@ lob_status lob_process_messages(lob_ctx *ctx, const int32_t *book_ids, int32_t n
   if (l2_mode < LOB_L2_NONE || l2_mode > LOB_L2_FINAL) return fail(ctx, LOB_EINVAL, "l2_mode");
   if (l2_mode != LOB_L2_NONE && !l2_out) return fail(ctx, LOB_EINVAL, "l2_out is NULL");
   DeviceGuard g(ctx->device);
-  lob::ProcArgs a = base_args(ctx, book_ids, n_books);
+  lob::ProcArgs a = lob::base_args(ctx, book_ids, n_books);
   a.msgs = msgs;
   a.offs = msg_offsets;
   a.l2_mode = l2_mode;
@@ -379,7 +344,7 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
   const int32_t *d_rows = d_ids + n_books;
   const int64_t *d_ranges =
       reinterpret_cast<const int64_t *>(ctx->d_stage + 2 * (size_t)n_books);
-  lob::ProcArgs a = base_args(ctx, d_ids, (int32_t)small.size());
+  lob::ProcArgs a = lob::base_args(ctx, d_ids, (int32_t)small.size());
   a.msgs = msgs;
   a.ranges = d_ranges;
   a.out_rows = d_rows;
@@ -540,7 +505,7 @@ lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, cons
   if (!l2_out) return fail(ctx, LOB_EINVAL, "l2_out is NULL");
   if (F > 0 && (!agent_fills || !agent_fill_counts)) return fail(ctx, LOB_EINVAL, "agent_fills is NULL");
   DeviceGuard g(ctx->device);
-  lob::ProcArgs a = base_args(ctx, book_ids, n_books);
+  lob::ProcArgs a = lob::base_args(ctx, book_ids, n_books);
   a.log = nullptr;
   a.msgs = W > 0 ? window : nullptr;
   a.w1 = W;

@@ -38,8 +38,8 @@ def test_library_exports_every_declared_symbol(libpath):
 
 
 def test_binding_declares_every_export(libpath):
-    from paper_2308_13289_amd import lob
-    assert sorted(lob.EXPORTS) == declared()
+    from paper_2308_13289_amd import lob, serve
+    assert sorted(lob.EXPORTS + serve.EXPORTS) == declared()
     lob.load(libpath)
 
 
