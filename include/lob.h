@@ -128,7 +128,10 @@ typedef struct {
                               (longest-processing-time list scheduling), 0 = as
                               listed                                            */
   int32_t books_per_block_big; /* books per workgroup of the second ragged launch */
-  int32_t reserved[2];
+  int32_t registers;       /* 1: each side's first 128 orders live in registers and
+                              only the orders past them use the LDS window / HBM;
+                              0: the whole window is in LDS                     */
+  int32_t reserved;
 } lob_plan;
 
 typedef struct lob_ctx lob_ctx;
@@ -244,10 +247,12 @@ lob_status lob_write_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books
 /* Empty the listed books, their trade logs and their counters. */
 lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, void *stream);
 
-/* Diagnostic: run the wavefront primitives the matcher is built on (prefix scan,
- * ballot, lane masks) on one wavefront and write 192 int32 results to out
- * (device): [0,64) inclusive prefix sums of (lane % 7 + 1), [64,128) number of
- * lanes <= lane with lane % 3 == 0, [128,192) number of lanes below lane. */
+/* Diagnostic: run the wavefront primitives the matcher is built on on one
+ * wavefront and write 384 int32 results to out (device), with x = 3*lane + 1:
+ * [0,64) inclusive prefix sums of (lane % 7 + 1); [64,128) number of lanes <=
+ * lane with lane % 3 == 0; [128,192) number of lanes below lane; [192,256) x of
+ * lane-1 (lane 0: -5); [256,320) x of lane+1 (lane 63: -7); [320,384) x of lane
+ * (lane+5) % 64. */
 lob_status lob_selftest(int32_t device, int32_t *out, void *stream);
 
 /* ---------------------------------------------------------------- serving */

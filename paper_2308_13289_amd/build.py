@@ -7,9 +7,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblob.so")
-SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_api.cpp"),
-           os.path.join(CSRC, "lob_serve.cpp")]
+SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_regbook.hip"),
+           os.path.join(CSRC, "lob_api.cpp"), os.path.join(CSRC, "lob_serve.cpp")]
 HEADERS = [os.path.join(CSRC, "lob_internal.h"), os.path.join(CSRC, "lob_ctx.h"),
+           os.path.join(CSRC, "lob_device.h"),
            os.path.join(ROOT, "include", "lob.h")]
 ARCH = os.environ.get("LOB_OFFLOAD_ARCH", "gfx950")
 
@@ -27,7 +28,7 @@ def command(out):
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-            SOURCES[0], "-x", "hip", SOURCES[1], SOURCES[2], "-o", out]
+            SOURCES[0], SOURCES[1], "-x", "hip", SOURCES[2], SOURCES[3], "-o", out]
 
 
 def up_to_date():

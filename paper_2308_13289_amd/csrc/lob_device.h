@@ -1,0 +1,105 @@
+// lob_device.h -- wavefront primitives and per-book state shared by the matching
+// kernels (lob_kernels.hip: book sides in LDS; lob_regbook.hip: the top of each
+// side in registers).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lob_internal.h"
+
+namespace lob {
+namespace dev {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+// The lane id as an opaque value: address arithmetic built on it is recomputed where
+// it is used instead of being hoisted out of the message loop into a VGPR per site.
+__device__ __forceinline__ int lane_id_local() {
+  int x;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(x));
+  return x;
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ int popc(uint64_t m) { return __builtin_popcountll(m); }
+__device__ __forceinline__ int first_set(uint64_t m) { return __builtin_ctzll(m); }
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni64(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffll));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+// lanes 0..lane inclusive
+__device__ __forceinline__ uint64_t mask_le() { return ~0ull >> (63 - lane_id()); }
+__device__ __forceinline__ uint64_t mask_lt() { return mask_le() >> 1; }
+
+// Inclusive prefix sum over the 64 lanes: four row_shr steps inside each row of 16
+// lanes, then row_bcast:15 and row_bcast:31 carry the row totals upwards.
+__device__ __forceinline__ int scan_incl(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); // row_bcast:15 -> rows 1,3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); // row_bcast:31 -> rows 2,3
+  return x;
+}
+
+// Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane l receives
+// lane l-1 (shr) or l+1 (shl); the lane with no source (0, resp. 63) receives `fill`.
+__device__ __forceinline__ int shr1(int x, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, x, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int shl1(int x, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, x, 0x130, 0xf, 0xf, false);
+}
+// Value of x in lane `src` (0..63) for every lane.
+__device__ __forceinline__ int from_lane(int x, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, x); }
+
+// Wave-uniform state of the book being processed.
+struct State {
+  int n[2];
+  int cap, flags;
+  long long n_msgs, n_trades, limit_qty, market_qty, traded_qty, cancelled_qty, market_discarded,
+      rejected_qty, cancel_miss;
+  int last_ts, last_tns, seen;
+  int32_t *log;        // this book's log segment, or nullptr
+  long long log_count, log_cap;
+  int32_t *fills;      // this book's fills row, or nullptr
+  int fill_cap, fill_count, agent_tid;
+};
+
+// Store the fills of one matching chunk (lanes with `takes` form the prefix
+// [0, ntr)) to the trade log and, when the book collects them, to the agent fills.
+__device__ __forceinline__ void emit(State &st, bool takes, int ntr, int P, int fill, int pas_oid,
+                                     int agg_oid, int ts, int tns, int pas_tid, int agg_tid) {
+  const int l = lane_id();
+  if (st.log) {
+    const long long room = st.log_cap - st.log_count;
+    if (takes && l < room) {
+      int2 *r = reinterpret_cast<int2 *>(st.log + (st.log_count + l) * kTradeFields);
+      r[0] = make_int2(P, fill);
+      r[1] = make_int2(pas_oid, agg_oid);
+      r[2] = make_int2(ts, tns);
+    }
+    const long long stored = room < ntr ? (room > 0 ? room : 0) : ntr;
+    if (stored < ntr) st.flags |= kFlagTradeFull;
+    st.log_count += stored;
+  }
+  if (st.fills) {
+    const bool ag = takes && (pas_tid == st.agent_tid || agg_tid == st.agent_tid);
+    const uint64_t ma = ballot(ag);
+    if (ma) {
+      const int k = st.fill_count + popc(ma & mask_lt());
+      if (ag && k < st.fill_cap) {
+        int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)k * kTradeFields);
+        r[0] = make_int2(P, fill);
+        r[1] = make_int2(pas_oid, agg_oid);
+        r[2] = make_int2(ts, tns);
+      }
+      st.fill_count += popc(ma);
+    }
+  }
+}
+
+}  // namespace dev
+}  // namespace lob

@@ -33,32 +33,13 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include "lob_device.h"
 #include "lob_internal.h"
 
 namespace lob {
 namespace {
 
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-__device__ __forceinline__ int popc(uint64_t m) { return __builtin_popcountll(m); }
-__device__ __forceinline__ int first_set(uint64_t m) { return __builtin_ctzll(m); }
-__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-// lanes 0..lane inclusive
-__device__ __forceinline__ uint64_t mask_le() { return ~0ull >> (63 - lane_id()); }
-__device__ __forceinline__ uint64_t mask_lt() { return mask_le() >> 1; }
-
-// Inclusive prefix sum over the 64 lanes: four row_shr steps inside each row of 16
-// lanes, then row_bcast:15 and row_bcast:31 carry the row totals upwards.
-__device__ __forceinline__ int scan_incl(int x) {
-  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
-  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); // row_bcast:15 -> rows 1,3
-  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); // row_bcast:31 -> rows 2,3
-  return x;
-}
+using namespace dev;
 
 // ---------------------------------------------------------------- book storage
 
@@ -74,19 +55,6 @@ struct View {
       return s < W ? lds + (sd * 3 + p) * W + s : hbm + (int64_t)(sd * 3 + p) * cap + s;
     }
   }
-};
-
-// Wave-uniform state of the book being processed.
-struct State {
-  int n[2];
-  int cap, flags;
-  long long n_msgs, n_trades, limit_qty, market_qty, traded_qty, cancelled_qty, market_discarded,
-      rejected_qty, cancel_miss;
-  int last_ts, last_tns, seen;
-  int32_t *log;        // this book's log segment, or nullptr
-  long long log_count, log_cap;
-  int32_t *fills;      // this book's fills row, or nullptr
-  int fill_cap, fill_count, agent_tid;
 };
 
 // Make the vector-memory stores of this wave visible to its later loads before
@@ -137,39 +105,6 @@ __device__ void shift_up(const View<SPILL> &B, int sd, int pos, int n) {
       *B.at(sd, 2, s + 1) = c;
     }
     spill_fence<SPILL>();
-  }
-}
-
-// Store the fills of one matching chunk (lanes with `takes` form the prefix
-// [0, ntr)) to the trade log and, when the book collects them, to the agent fills.
-__device__ __forceinline__ void emit(State &st, bool takes, int ntr, int P, int fill, int pas_oid,
-                                     int agg_oid, int ts, int tns, int pas_tid, int agg_tid) {
-  const int l = lane_id();
-  if (st.log) {
-    const long long room = st.log_cap - st.log_count;
-    if (takes && l < room) {
-      int2 *r = reinterpret_cast<int2 *>(st.log + (st.log_count + l) * kTradeFields);
-      r[0] = make_int2(P, fill);
-      r[1] = make_int2(pas_oid, agg_oid);
-      r[2] = make_int2(ts, tns);
-    }
-    const long long stored = room < ntr ? (room > 0 ? room : 0) : ntr;
-    if (stored < ntr) st.flags |= kFlagTradeFull;
-    st.log_count += stored;
-  }
-  if (st.fills) {
-    const bool ag = takes && (pas_tid == st.agent_tid || agg_tid == st.agent_tid);
-    const uint64_t ma = ballot(ag);
-    if (ma) {
-      const int k = st.fill_count + popc(ma & mask_lt());
-      if (ag && k < st.fill_cap) {
-        int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)k * kTradeFields);
-        r[0] = make_int2(P, fill);
-        r[1] = make_int2(pas_oid, agg_oid);
-        r[2] = make_int2(ts, tns);
-      }
-      st.fill_count += popc(ma);
-    }
   }
 }
 
@@ -397,21 +332,21 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
   st.n[1] = uni(h->n[1]);
   st.cap = uni(h->cap);
   st.flags = uni(h->flags);
-  st.n_msgs = h->n_msgs;
-  st.n_trades = h->n_trades;
-  st.limit_qty = h->limit_qty;
-  st.market_qty = h->market_qty;
-  st.traded_qty = h->traded_qty;
-  st.cancelled_qty = h->cancelled_qty;
-  st.market_discarded = h->market_discarded;
-  st.rejected_qty = h->rejected_qty;
-  st.cancel_miss = h->cancel_miss;
+  st.n_msgs = uni64(h->n_msgs);
+  st.n_trades = uni64(h->n_trades);
+  st.limit_qty = uni64(h->limit_qty);
+  st.market_qty = uni64(h->market_qty);
+  st.traded_qty = uni64(h->traded_qty);
+  st.cancelled_qty = uni64(h->cancelled_qty);
+  st.market_discarded = uni64(h->market_discarded);
+  st.rejected_qty = uni64(h->rejected_qty);
+  st.cancel_miss = uni64(h->cancel_miss);
   st.last_ts = uni(h->last_ts);
   st.last_tns = uni(h->last_tns);
   st.seen = uni(h->seen_time);
-  const long long log_off = h->log_off;
-  st.log_cap = h->log_cap;
-  st.log_count = h->log_count;
+  const long long log_off = uni64(h->log_off);
+  st.log_cap = uni64(h->log_cap);
+  st.log_count = uni64(h->log_count);
   st.log = a.log ? a.log + log_off * kTradeFields : nullptr;
   const int row = a.out_rows ? uni(a.out_rows[i]) : i;  // output row of this book
   st.fills = a.fills ? a.fills + (int64_t)row * a.fill_cap * kTradeFields : nullptr;
@@ -421,7 +356,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
 
   View<SPILL> B;
   B.lds = lds;
-  B.hbm = a.books + h->book_off;
+  B.hbm = a.books + uni64(h->book_off);
   B.W = a.W;
   B.cap = st.cap;
 
@@ -487,7 +422,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
 template <bool SPILL>
 __global__ void __launch_bounds__(1024) k_process(ProcArgs a) {
   extern __shared__ int2 smem[];
-  const int w = threadIdx.x / kWave;
+  const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * a.bpb + w;
   if (i >= a.n) return;
   int2 *lds = smem + (int64_t)w * a.lds_int2_per_wave;
@@ -552,7 +487,7 @@ __global__ void k_status(const BookHdr *hdr, const int32_t *ids, int n, int n_to
 __global__ void __launch_bounds__(256) k_read_l2(const BookHdr *hdr, int2 *books, const int32_t *ids, int n,
                                                   int n_total, int L, int32_t *out) {
   __shared__ int scratch_all[4 * 64];
-  const int w = threadIdx.x / kWave;
+  const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
   const int b = ids ? uni(ids[i]) : i;
@@ -572,7 +507,7 @@ __global__ void __launch_bounds__(256) k_read_l2(const BookHdr *hdr, int2 *books
 // Book dump [n][2][dump_cap][6]: one wave per listed book.
 __global__ void __launch_bounds__(256) k_read_book(const BookHdr *hdr, const int2 *books, const int32_t *ids,
                                                     int n, int n_total, int dump_cap, int32_t *out) {
-  const int w = threadIdx.x / kWave;
+  const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
   const int l = lane_id();
@@ -602,7 +537,7 @@ __global__ void __launch_bounds__(256) k_read_book(const BookHdr *hdr, const int
 // Load a book dump: rows taken in order up to the first with Q <= 0 or the capacity.
 __global__ void __launch_bounds__(256) k_write_book(BookHdr *hdr, int2 *books, const int32_t *ids, int n,
                                                      int n_total, int dump_cap, const int32_t *in) {
-  const int w = threadIdx.x / kWave;
+  const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
   const int l = lane_id();

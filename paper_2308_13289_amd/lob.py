@@ -42,7 +42,7 @@ class Plan(ctypes.Structure):
     _fields_ = [("lds_slots", ctypes.c_int32), ("books_per_block", ctypes.c_int32),
                 ("ragged_split", ctypes.c_int32), ("lds_slots_big", ctypes.c_int32),
                 ("ragged_order", ctypes.c_int32), ("books_per_block_big", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("registers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -122,7 +122,7 @@ def _stream(stream, device):
 
 
 def selftest(device=0):
-    out = torch.empty(192, dtype=torch.int32, device=f"cuda:{device}")
+    out = torch.empty(384, dtype=torch.int32, device=f"cuda:{device}")
     st = load().lob_selftest(device, _ptr(out), _stream(None, out.device))
     if st != OK:
         raise LobError(st, "selftest launch failed")

@@ -38,14 +38,22 @@ def test_selftest_primitives():
     np.testing.assert_array_equal(out[:64], np.cumsum(lanes % 7 + 1))
     np.testing.assert_array_equal(out[64:128], np.cumsum(lanes % 3 == 0))
     np.testing.assert_array_equal(out[128:192], lanes)
+    x = 3 * lanes + 1
+    np.testing.assert_array_equal(out[192:256], np.concatenate([[-5], x[:-1]]))
+    np.testing.assert_array_equal(out[256:320], np.concatenate([x[1:], [-7]]))
+    np.testing.assert_array_equal(out[320:384], x[(lanes + 5) % 64])
 
 
-def test_golden_cases_on_gpu():
+RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}}
+
+
+@pytest.mark.parametrize("res", ["regs", "lds"])
+def test_golden_cases_on_gpu(res):
     cases = all_cases()
     caps = np.array([c.cap for c in cases], np.int32)
     msgs = np.concatenate([c.msgs for c in cases])
     offs = np.concatenate([[0], np.cumsum([len(c.msgs) for c in cases])]).astype(np.int64)
-    g = run_gpu(caps, msgs, offs, levels=3, l2_mode=lob.L2_FINAL)
+    g = run_gpu(caps, msgs, offs, levels=3, l2_mode=lob.L2_FINAL, plan=RESIDENCY[res])
     for i, c in enumerate(cases):
         tr = g["trades"][g["trade_offs"][i]:g["trade_offs"][i + 1]]
         np.testing.assert_array_equal(tr, c.trades[:, 1:].astype(np.int32), err_msg=c.name)
@@ -61,21 +69,23 @@ def test_golden_cases_on_gpu():
             assert g["status"][k][i] == v, (c.name, k)
 
 
+@pytest.mark.parametrize("res", ["regs", "lds"])
 @pytest.mark.parametrize("cap", [1, 2])
-def test_bruteforce_sequences_on_gpu(cap):
+def test_bruteforce_sequences_on_gpu(cap, res):
     streams = [to_msgs(s) for s in itertools.product(alphabet(), repeat=3)]
     msgs = np.array([m for s in streams for m in s], np.int32)
     offs = np.concatenate([[0], np.cumsum([len(s) for s in streams])]).astype(np.int64)
     caps = np.full(len(streams), cap, np.int32)
-    g = run_gpu(caps, msgs, offs, levels=2, l2_mode=lob.L2_PER_MESSAGE)
+    g = run_gpu(caps, msgs, offs, levels=2, l2_mode=lob.L2_PER_MESSAGE, plan=RESIDENCY[res])
     o = run_oracle(caps, msgs, offs, levels=2, l2_mode=O.L2_PER_MESSAGE)
     assert_same(g, o, f"brute force cap {cap}")
 
 
-def test_c0_full_parity_per_message_l2():
+@pytest.mark.parametrize("res", ["regs", "lds"])
+def test_c0_full_parity_per_message_l2(res):
     """64 books x (100 seeds + 1000 messages), capacity 100, L2 after every message."""
     w = W.c0()
-    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_PER_MESSAGE)
+    g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_PER_MESSAGE, plan=RESIDENCY[res])
     o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_PER_MESSAGE)
     assert_same(g, o, "c0")
     assert o["stats"]["n_trades"].sum() > 30000
@@ -87,7 +97,9 @@ def test_c0_full_parity_per_message_l2():
     pytest.param({"persistent": 1}, marks=WITHDRAWN),
     {"lds_slots": 64},                      # books past 64 orders spill to HBM
     pytest.param({"lds_slots": 64, "persistent": 1}, marks=WITHDRAWN),
-], ids=["bpb1", "bpb8", "persistent", "spill64", "spill64_persistent"])
+    {"registers": 0, "books_per_block": 8},
+    {"registers": 0, "lds_slots": 64},
+], ids=["bpb1", "bpb8", "persistent", "spill64", "spill64_persistent", "lds_bpb8", "lds_spill64"])
 def test_plans_agree_c0(plan):
     w = W.c0()
     g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, plan=plan)
@@ -103,7 +115,10 @@ def test_plans_agree_c0(plan):
                  marks=WITHDRAWN),
     pytest.param({"persistent": 1, "lds_slots": 128, "split_buckets": 1, "lds_slots_big": 256},
                  marks=WITHDRAWN),
-], ids=["default", "spill128", "persistent", "split", "split_spill"])
+    {"registers": 0},
+    {"registers": 0, "lds_slots": 128},
+    {"lds_slots": 200},
+], ids=["default", "spill128", "persistent", "split", "split_spill", "lds", "lds_spill128", "regs_tail200"])
 def test_ragged_mixed_capacities(plan):
     """Capacities {50,100,500,1000} and uneven stream lengths in one call."""
     w = W.ragged(n_books=96, max_flow=4000)
@@ -158,23 +173,28 @@ def test_small_capacity_rejects_and_deep_books():
     assert o["stats"]["rejected_qty"].sum() > 0
     rng = np.random.default_rng(7)
     streams = []
-    for b in range(8):
+    for b in range(16):
+        S = 1 if b % 2 == 0 else -1  # the deep side: bids for even books, asks for odd
         ms, t = [], 0
-        for k in range(260):  # bids at many prices, some repeated
-            ms.append([1, 1, int(rng.integers(900, 1000)), int(rng.integers(1, 50)), k + 1, 3, 34200, t])
+        for k in range(260):  # resting orders at many prices, some repeated
+            ms.append([1, S, int(rng.integers(900, 1000)), int(rng.integers(1, 50)), k + 1, 3, 34200, t])
             t += 1
-        for k in range(40):  # cancels of live and dead ids, then sweeping sells
-            ms.append([2, 1, 0, int(rng.integers(1, 30)), int(rng.integers(1, 260)), 3, 34200, t])
+        for k in range(40):  # cancels of live and dead ids (some deep in the side)
+            ms.append([2, S, 0, int(rng.integers(1, 30)), int(rng.integers(1, 260)), 3, 34200, t])
             t += 1
-        for k in range(6):
-            ms.append([1, -1, int(rng.integers(900, 1000)), int(rng.integers(50, 3000)), 1000 + k, 4, 34200, t])
+        for k in range(6):  # sweeps of many orders, remainders rest on the other side
+            ms.append([1, -S, int(rng.integers(900, 1000)), int(rng.integers(50, 3000)), 1000 + k, 4, 34200, t])
             t += 1
-        ms.append([4, -1, 0, 5000, 2000, 4, 34200, t])
+        for k in range(30):  # more orders on both sides, then a cancel of a deep one
+            ms.append([1, S, int(rng.integers(850, 950)), int(rng.integers(1, 50)), 3000 + k, 3, 34200, t])
+            t += 1
+        ms.append([3, S, 0, 100, 3005, 3, 34200, t])
+        ms.append([4, -S, 0, 5000, 2000, 4, 34200, t + 1])
         streams.append(ms)
     msgs = np.array([m for s in streams for m in s], np.int32)
     offs = np.concatenate([[0], np.cumsum([len(s) for s in streams])]).astype(np.int64)
-    caps = np.full(8, 300, np.int32)
-    for plan in ({}, {"lds_slots": 64}):
+    caps = np.full(16, 300, np.int32)
+    for plan in ({}, {"lds_slots": 64}, {"lds_slots": 200}, {"registers": 0}, {"registers": 0, "lds_slots": 64}):
         g = run_gpu(caps, msgs, offs, l2_mode=lob.L2_PER_MESSAGE, plan=plan)
         o = run_oracle(caps, msgs, offs, l2_mode=O.L2_PER_MESSAGE)
         assert_same(g, o, f"deep books {plan}")
