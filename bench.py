@@ -404,12 +404,27 @@ def bench_step(args, n_books=8192, n_steps=1000, window=100, fills_cap=32):
     return res
 
 
+def bench_copy(args, nbytes=1 << 30):
+    """Calibration for HBM byte counters: one device-to-device copy of a known size
+    (reads nbytes, writes nbytes)."""
+    dev = torch.device("cuda:0")
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": "copy calibration", "bytes_read": nbytes, "bytes_written": nbytes, "s": dt,
+            "GB_per_s": 2 * nbytes / dt / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3", "c4", "copy"])
     ap.add_argument("--tune-trials", type=int, default=16)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
@@ -431,6 +446,9 @@ def main():
         return
     if args.workload == "c4":
         print(json.dumps(bench_serving(args)), flush=True)
+        return
+    if args.workload == "copy":
+        print(json.dumps(bench_copy(args)), flush=True)
         return
     t0 = time.perf_counter()
     if args.workload in ("c1", "all"):
