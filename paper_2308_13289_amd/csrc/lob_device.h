@@ -66,6 +66,7 @@ struct State {
   long long log_count, log_cap;
   int32_t *fills;      // this book's fills row, or nullptr
   int fill_cap, fill_count, agent_tid;
+  int bP[2], bQ[2], bO[2], bT[2];  // slot 0 of each side (valid while n > 0)
 };
 
 // Store the fills of one matching chunk (lanes with `takes` form the prefix
@@ -98,6 +99,34 @@ __device__ __forceinline__ void emit(State &st, bool takes, int ntr, int P, int 
       }
       st.fill_count += popc(ma);
     }
+  }
+}
+
+// One trade from scalar values (lane 0 writes it).
+__device__ __forceinline__ void emit_one(State &st, int P, int fill, int pas_oid, int agg_oid, int ts, int tns,
+                                         int pas_tid, int agg_tid) {
+  const bool lead = lane_id() == 0;
+  if (st.log) {
+    if (st.log_count < st.log_cap) {
+      if (lead) {
+        int2 *r = reinterpret_cast<int2 *>(st.log + st.log_count * kTradeFields);
+        r[0] = make_int2(P, fill);
+        r[1] = make_int2(pas_oid, agg_oid);
+        r[2] = make_int2(ts, tns);
+      }
+      st.log_count++;
+    } else {
+      st.flags |= kFlagTradeFull;
+    }
+  }
+  if (st.fills && (pas_tid == st.agent_tid || agg_tid == st.agent_tid)) {
+    if (st.fill_count < st.fill_cap && lead) {
+      int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)st.fill_count * kTradeFields);
+      r[0] = make_int2(P, fill);
+      r[1] = make_int2(pas_oid, agg_oid);
+      r[2] = make_int2(ts, tns);
+    }
+    st.fill_count++;
   }
 }
 

@@ -108,20 +108,54 @@ __device__ void shift_up(const View<SPILL> &B, int sd, int pos, int n) {
   }
 }
 
-// Matching loop of Section 4.1 for an aggressor on the side opposite to `opp`
-// with limit price `lim` and quantity q.  Returns the unfilled quantity.
+// Slot 0 (the best order) of a side, kept in scalar registers so that the common
+// cases -- a limit that does not cross, an aggressor filled by the best order
+// alone, a cancel of the best order -- need no pass over the side.
 template <bool SPILL>
-__device__ int match(const View<SPILL> &B, State &st, int opp, int lim, int q, int a_oid, int a_tid,
-                     int ts, int tns) {
+__device__ __forceinline__ void load_best(const View<SPILL> &B, State &st, int sd) {
+  if (st.n[sd] > 0) {
+    const int2 pq = *B.at(sd, 0, 0);
+    const int2 ot = *B.at(sd, 1, 0);
+    st.bP[sd] = uni(pq.x);
+    st.bQ[sd] = uni(pq.y);
+    st.bO[sd] = uni(ot.x);
+    st.bT[sd] = uni(ot.y);
+  }
+}
+
+// Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
+// with limit price lim and quantity q.  Returns the unfilled quantity.
+template <int OPP, bool SPILL>
+__device__ __forceinline__ int match(const View<SPILL> &B, State &st, int lim, int q, int a_oid, int a_tid,
+                                     int ts, int tns) {
+  const int n = st.n[OPP];
+  constexpr bool buyer = (OPP == 0);
+  if (q <= 0 || n == 0) return q;
+  if (buyer ? st.bP[OPP] > lim : st.bP[OPP] < lim) return q;  // the best standing price does not overlap
+  if (q <= st.bQ[OPP]) {
+    // Q_s' = Q_s - Q_a >= 0: one trade with the best order, the aggressor is done
+    emit_one(st, st.bP[OPP], q, st.bO[OPP], a_oid, ts, tns, st.bT[OPP], a_tid);
+    st.traded_qty += q;
+    st.n_trades++;
+    if (q < st.bQ[OPP]) {
+      st.bQ[OPP] -= q;
+      if (lane_id() == 0) *B.at(OPP, 0, 0) = make_int2(st.bP[OPP], st.bQ[OPP]);
+      spill_fence<SPILL>();
+    } else {
+      shift_down(B, OPP, 0, 1, n);
+      st.n[OPP] = n - 1;
+      load_best(B, st, OPP);
+    }
+    return 0;
+  }
+  // the aggressor outlasts the best order: one prefix scan per 64 crossing orders
   const int l = lane_id();
-  const int n = st.n[opp];
-  const bool buyer = (opp == 0);
   int removed = 0;
   for (int base = 0; base < n && q > 0; base += kWave) {
     const int s = base + l;
     const bool valid = s < n;
     int2 pq = make_int2(0, 0);
-    if (valid) pq = *B.at(opp, 0, s);
+    if (valid) pq = *B.at(OPP, 0, s);
     const bool cross = valid && (buyer ? pq.x <= lim : pq.x >= lim);
     const int qv = cross ? pq.y : 0;
     const int incl = scan_incl(qv);
@@ -136,8 +170,8 @@ __device__ int match(const View<SPILL> &B, State &st, int opp, int lim, int q, i
     int2 ot = make_int2(0, 0);
     if (takes) {
       fill = min(qv, q - excl);
-      ot = *B.at(opp, 1, s);
-      if (!full) *B.at(opp, 0, s) = make_int2(pq.x, pq.y - fill);
+      ot = *B.at(OPP, 1, s);
+      if (!full) *B.at(OPP, 0, s) = make_int2(pq.x, pq.y - fill);
     }
     emit(st, takes, ntr, pq.x, fill, ot.x, a_oid, ts, tns, ot.y, a_tid);
     const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
@@ -149,72 +183,90 @@ __device__ int match(const View<SPILL> &B, State &st, int opp, int lim, int q, i
   }
   spill_fence<SPILL>();
   if (removed > 0) {
-    shift_down(B, opp, 0, removed, n);
-    st.n[opp] = n - removed;
+    shift_down(B, OPP, 0, removed, n);
+    st.n[OPP] = n - removed;
   }
+  load_best(B, st, OPP);
   return q;
 }
 
-// Add (Section 4.1, item 1): the new order goes behind every order with an equal
-// or better price, i.e. at its price-time position.
-template <bool SPILL>
-__device__ void insert(const View<SPILL> &B, State &st, int sd, int P, int Q, int oid, int tid, int ts,
-                       int tns) {
+// Add (Section 4.1, item 1) on side SD: the new order goes behind every order with
+// an equal or better price, i.e. at its price-time position.
+template <int SD, bool SPILL>
+__device__ __forceinline__ void insert(const View<SPILL> &B, State &st, int P, int Q, int oid, int tid, int ts,
+                                       int tns) {
   const int l = lane_id();
-  const int n = st.n[sd];
+  const int n = st.n[SD];
   if (n >= st.cap) {
     st.rejected_qty += Q;
     st.flags |= kFlagSideFull;
     return;
   }
   int pos = 0;
-  for (int base = 0; base < n; base += kWave) {
-    const int s = base + l;
-    bool ahead = false;
-    if (s < n) {
-      const int p = B.at(sd, 0, s)->x;
-      ahead = (sd == 1) ? p >= P : p <= P;
+  // strictly better than the best order: it becomes slot 0, no search needed
+  if (n > 0 && !(SD == 1 ? P > st.bP[SD] : P < st.bP[SD])) {
+    for (int base = 0; base < n; base += kWave) {
+      const int s = base + l;
+      bool ahead = false;
+      if (s < n) {
+        const int p = B.at(SD, 0, s)->x;
+        ahead = (SD == 1) ? p >= P : p <= P;
+      }
+      const int k = popc(ballot(ahead));
+      pos += k;
+      if (k < kWave) break;
     }
-    const int k = popc(ballot(ahead));
-    pos += k;
-    if (k < kWave) break;
   }
-  if (pos < n) shift_up(B, sd, pos, n);
+  if (pos < n) shift_up(B, SD, pos, n);
   if (l == 0) {
-    *B.at(sd, 0, pos) = make_int2(P, Q);
-    *B.at(sd, 1, pos) = make_int2(oid, tid);
-    *B.at(sd, 2, pos) = make_int2(ts, tns);
+    *B.at(SD, 0, pos) = make_int2(P, Q);
+    *B.at(SD, 1, pos) = make_int2(oid, tid);
+    *B.at(SD, 2, pos) = make_int2(ts, tns);
   }
   spill_fence<SPILL>();
-  st.n[sd] = n + 1;
+  st.n[SD] = n + 1;
+  if (pos == 0) {
+    st.bP[SD] = P;
+    st.bQ[SD] = Q;
+    st.bO[SD] = oid;
+    st.bT[SD] = tid;
+  }
 }
 
-// Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders).
-template <bool SPILL>
-__device__ void cancel(const View<SPILL> &B, State &st, int sd, int oid, int qty, int price) {
+// Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders) on side SD.
+template <int SD, bool SPILL>
+__device__ __forceinline__ void cancel(const View<SPILL> &B, State &st, int oid, int qty, int price) {
   if (qty <= 0) return;
   const int l = lane_id();
-  const int n = st.n[sd];
-  int k = -1;
-  for (int base = 0; base < n; base += kWave) {
-    const int s = base + l;
-    bool hit = false;
-    if (s < n) hit = B.at(sd, 1, s)->x == oid;
-    const uint64_t m = ballot(hit);
-    if (m) {
-      k = base + first_set(m);
-      break;
-    }
+  const int n = st.n[SD];
+  if (n == 0) {
+    st.cancel_miss++;
+    return;
   }
-  if (k < 0) {
+  int k = -1;
+  if (st.bO[SD] == oid) {
+    k = 0;  // the best order: the first order with this id in priority order
+  } else {
     for (int base = 0; base < n; base += kWave) {
       const int s = base + l;
       bool hit = false;
-      if (s < n) hit = B.at(sd, 1, s)->x <= -9000 && B.at(sd, 0, s)->x == price;
+      if (s < n) hit = B.at(SD, 1, s)->x == oid;
       const uint64_t m = ballot(hit);
       if (m) {
         k = base + first_set(m);
         break;
+      }
+    }
+    if (k < 0) {
+      for (int base = 0; base < n; base += kWave) {
+        const int s = base + l;
+        bool hit = false;
+        if (s < n) hit = B.at(SD, 1, s)->x <= -9000 && B.at(SD, 0, s)->x == price;
+        const uint64_t m = ballot(hit);
+        if (m) {
+          k = base + first_set(m);
+          break;
+        }
       }
     }
   }
@@ -222,16 +274,18 @@ __device__ void cancel(const View<SPILL> &B, State &st, int sd, int oid, int qty
     st.cancel_miss++;
     return;
   }
-  const int2 pq = *B.at(sd, 0, k);
+  const int2 pq = *B.at(SD, 0, k);
   const int P = uni(pq.x), Q = uni(pq.y);
   st.cancelled_qty += min(qty, Q);
   const int left = Q - qty;
   if (left > 0) {
-    if (l == 0) *B.at(sd, 0, k) = make_int2(P, left);
+    if (l == 0) *B.at(SD, 0, k) = make_int2(P, left);
     spill_fence<SPILL>();
+    if (k == 0) st.bQ[SD] = left;
   } else {
-    shift_down(B, sd, k, 1, n);
-    st.n[sd] = n - 1;
+    shift_down(B, SD, k, 1, n);
+    st.n[SD] = n - 1;
+    if (k == 0) load_best(B, st, SD);
   }
 }
 
@@ -275,48 +329,88 @@ __device__ __forceinline__ void write_l2(const View<SPILL> &B, const State &st, 
   l2_side(B, st, 1, L, o + L, scratch);
 }
 
-// One message (Section 4.2).  Side index: 0 asks, 1 bids.
+// One message (Section 4.2) given its case code (see process_all).
 template <bool SPILL>
-__device__ __forceinline__ void process_msg(const View<SPILL> &B, State &st, int T, int S, int P, int Q,
-                                            int oid, int tid, int ts, int tns) {
-  st.n_msgs++;
-  if (T < 1 || T > 4 || (S != 1 && S != -1)) return;
-  if (st.seen && (ts < st.last_ts || (ts == st.last_ts && tns < st.last_tns))) st.flags |= kFlagTimeOrder;
-  st.seen = 1;
-  st.last_ts = ts;
-  st.last_tns = tns;
-  const int own = (S == 1) ? 1 : 0;
-  const int opp = 1 - own;
-  if (T == 1) {
-    if (Q > 0) st.limit_qty += Q;
-    const int rem = match(B, st, opp, P, Q, oid, tid, ts, tns);
-    if (rem > 0) insert(B, st, own, P, rem, oid, tid, ts, tns);
-  } else if (T == 4) {
-    if (Q > 0) st.market_qty += Q;
-    const int rem = match(B, st, opp, S == 1 ? INT_MAX : 0, Q, oid, tid, ts, tns);
-    if (rem > 0) st.market_discarded += rem;
+__device__ __forceinline__ void process_msg(const View<SPILL> &B, State &st, int code, int P, int Q, int oid,
+                                            int tid, int ts, int tns) {
+  if (code == 0) return;  // padding / unknown type or side: never processed
+  const bool buys = (code & 1) == 0;  // even codes are buy-side messages
+  if (code <= 4) {
+    // limit (1, 2): match, then rest the remainder as one new order (item 1);
+    // market (3, 4): match at price 0 (sell) / max_int (buy), drop the rest (item 3)
+    const bool limit = code <= 2;
+    if (Q > 0) {
+      if (limit)
+        st.limit_qty += Q;
+      else
+        st.market_qty += Q;
+    }
+    const int lim = limit ? P : (buys ? INT_MAX : 0);
+    const int rem = buys ? match<0>(B, st, lim, Q, oid, tid, ts, tns) : match<1>(B, st, lim, Q, oid, tid, ts, tns);
+    if (rem > 0) {
+      if (!limit)
+        st.market_discarded += rem;
+      else if (buys)
+        insert<1>(B, st, P, rem, oid, tid, ts, tns);
+      else
+        insert<0>(B, st, P, rem, oid, tid, ts, tns);
+    }
   } else {
-    cancel(B, st, own, oid, Q, P);
+    // cancel and delete (5, 6) are the same operation (item 2)
+    if (buys)
+      cancel<1>(B, st, oid, Q, P);
+    else
+      cancel<0>(B, st, oid, Q, P);
   }
 }
 
+// The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
+// form's agent orders) msgs2[beg2, beg2 + n2).  They are read in 64-message chunks,
+// one record per lane; per chunk the lanes work out each message's case code
+// (1/2 limit sell/buy, 3/4 market sell/buy, 5/6 cancel-or-delete on the ask/bid
+// side, 0 skipped), the message count and the check that valid messages' times do
+// not decrease, so the scalar path per message only dispatches.
 template <bool SPILL>
-__device__ void process_range(const View<SPILL> &B, State &st, const ProcArgs &a, const int32_t *msgs,
-                              long long beg, long long end, bool l2_each, int *scratch) {
+__device__ __forceinline__ void process_all(const View<SPILL> &B, State &st, const ProcArgs &a, long long beg1,
+                                            long long n1, long long beg2, long long n2, bool l2_each,
+                                            int *scratch) {
   const int l = lane_id();
-  for (long long m0 = beg; m0 < end; m0 += kWave) {
-    const int cnt = (int)((end - m0) < kWave ? (end - m0) : kWave);
+  const long long total = n1 + n2;
+  for (long long k0 = 0; k0 < total; k0 += kWave) {
+    const int cnt = (int)((total - k0) < kWave ? (total - k0) : kWave);
     int4 u = make_int4(0, 0, 0, 0), v = make_int4(0, 0, 0, 0);
     if (l < cnt) {
-      const int4 *mp = reinterpret_cast<const int4 *>(msgs + (m0 + l) * kMsgFields);
+      const long long k = k0 + l;
+      const int32_t *rec = k < n1 ? a.msgs + (beg1 + k) * kMsgFields : a.msgs2 + (beg2 + k - n1) * kMsgFields;
+      const int4 *mp = reinterpret_cast<const int4 *>(rec);
       u = mp[0];
       v = mp[1];
     }
+    const int T = u.x, S = u.y;
+    const bool ok = l < cnt && T >= 1 && T <= 4 && (S == 1 || S == -1);
+    const int code = !ok ? 0 : (T == 1 ? 1 : T == 4 ? 3 : 5) + (S == 1 ? 1 : 0);
+    // times of valid messages must not decrease (R2): compare with the previous
+    // valid lane, or with the last valid time before this chunk
+    const uint64_t vmask = ballot(ok);
+    if (vmask) {
+      const uint64_t below = vmask & mask_lt();
+      const int src = below ? 63 - __builtin_clzll(below) : 0;
+      const int pts = from_lane(v.z, src), ptns = from_lane(v.w, src);
+      const bool has_prev = below != 0 || st.seen;
+      const int cts = below ? pts : st.last_ts, ctns = below ? ptns : st.last_tns;
+      const bool dec = ok && has_prev && (v.z < cts || (v.z == cts && v.w < ctns));
+      if (ballot(dec)) st.flags |= kFlagTimeOrder;
+      const int top = 63 - __builtin_clzll(vmask);
+      st.last_ts = rdlane(v.z, top);
+      st.last_tns = rdlane(v.w, top);
+      st.seen = 1;
+    }
+    st.n_msgs += cnt;
     for (int j = 0; j < cnt; ++j) {
-      const int T = rdlane(u.x, j), S = rdlane(u.y, j), P = rdlane(u.z, j), Q = rdlane(u.w, j);
-      const int oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j), tns = rdlane(v.w, j);
-      process_msg(B, st, T, S, P, Q, oid, tid, ts, tns);
-      if (l2_each) write_l2(B, st, a.levels, a.l2_out + (m0 + j) * 4 * a.levels, scratch);
+      const int c = rdlane(code, j);
+      process_msg(B, st, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
+                  rdlane(v.w, j));
+      if (l2_each && k0 + j < n1) write_l2(B, st, a.levels, a.l2_out + (beg1 + k0 + j) * 4 * a.levels, scratch);
     }
   }
 }
@@ -344,10 +438,9 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
   st.last_ts = uni(h->last_ts);
   st.last_tns = uni(h->last_tns);
   st.seen = uni(h->seen_time);
-  const long long log_off = uni64(h->log_off);
   st.log_cap = uni64(h->log_cap);
   st.log_count = uni64(h->log_count);
-  st.log = a.log ? a.log + log_off * kTradeFields : nullptr;
+  st.log = a.log ? a.log + uni64(h->log_off) * kTradeFields : nullptr;
   const int row = a.out_rows ? uni(a.out_rows[i]) : i;  // output row of this book
   st.fills = a.fills ? a.fills + (int64_t)row * a.fill_cap * kTradeFields : nullptr;
   st.fill_cap = a.fill_cap;
@@ -367,25 +460,24 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
       for (int base = 0; base < nw; base += kWave)
         if (base + l < nw) lds[(sd * 3 + p) * a.W + base + l] = B.hbm[(int64_t)(sd * 3 + p) * st.cap + base + l];
   }
+  load_best(B, st, 0);
+  load_best(B, st, 1);
 
+  long long beg1 = 0, n1 = 0;
   if (a.msgs) {
-    long long beg, end;
     if (a.ranges) {
-      beg = a.ranges[2 * i];
-      end = a.ranges[2 * i + 1];
+      beg1 = a.ranges[2 * i];
+      n1 = a.ranges[2 * i + 1] - beg1;
     } else if (a.offs) {
-      beg = a.offs[i];
-      end = a.offs[i + 1];
+      beg1 = a.offs[i];
+      n1 = a.offs[i + 1] - beg1;
     } else {
-      beg = (long long)i * a.w1;
-      end = beg + a.w1;
+      beg1 = (long long)i * a.w1;
+      n1 = a.w1;
     }
-    process_range(B, st, a, a.msgs, beg, end, a.l2_mode == 1, scratch);
   }
-  if (a.msgs2 && a.w2 > 0) {
-    const long long beg = (long long)i * a.w2;
-    process_range(B, st, a, a.msgs2, beg, beg + a.w2, false, scratch);
-  }
+  const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
+  process_all(B, st, a, beg1, n1, (long long)i * a.w2, n2, a.l2_mode == 1, scratch);
   if (a.l2_mode == 2) write_l2(B, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels, scratch);
 
   // LDS window -> HBM
