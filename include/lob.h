@@ -128,9 +128,10 @@ typedef struct {
                               (longest-processing-time list scheduling), 0 = as
                               listed                                            */
   int32_t books_per_block_big; /* books per workgroup of the second ragged launch */
-  int32_t registers;       /* 1: each side's first 128 orders live in registers and
-                              only the orders past them use the LDS window / HBM;
-                              0: the whole window is in LDS                     */
+  int32_t registers;       /* 1: a launch whose books all have capacity <= 128
+                              keeps each whole book in registers while its
+                              messages run (larger books use the LDS window);
+                              0: always the LDS window                          */
   int32_t reserved;
 } lob_plan;
 

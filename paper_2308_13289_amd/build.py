@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblob.so")
-SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_regbook.hip"),
+SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_small.hip"),
            os.path.join(CSRC, "lob_api.cpp"), os.path.join(CSRC, "lob_serve.cpp")]
 HEADERS = [os.path.join(CSRC, "lob_internal.h"), os.path.join(CSRC, "lob_ctx.h"),
            os.path.join(CSRC, "lob_device.h"),

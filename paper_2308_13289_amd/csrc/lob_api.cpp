@@ -65,13 +65,9 @@ lob_status check_list(lob_ctx *c, int32_t n) {
   return LOB_OK;
 }
 
-// LDS words (int2) one wave needs for a window of W slots per side: 3 pair arrays
-// per side for the slots kept in LDS (all W, or those past the register-resident
-// ones), plus L ints of L2 scratch.
-int lds_int2_per_wave(int W, int L, bool regs) {
-  const int in_lds = regs ? std::max(0, W - lob::regbook_slots()) : W;
-  return 6 * in_lds + (L + 1) / 2;
-}
+// LDS words (int2) one wave of the LDS kernel needs for a window of W slots per
+// side: 3 pair arrays per side, plus L ints of L2 scratch.
+int lds_int2_per_wave(int W, int L) { return 6 * W + (L + 1) / 2; }
 
 struct Geometry {
   int W;
@@ -82,12 +78,10 @@ struct Geometry {
 
 // Window and books-per-block for one launch over books of capacity <= cap_limit.
 lob_status geometry(lob_ctx *c, int window, int cap_limit, int bpb_want, Geometry *g) {
-  const bool regs = c->plan.registers != 0;
   int W = std::min(window, cap_limit);
-  if (regs) W = std::max(W, lob::regbook_slots());
   if (W < 1) W = 1;
   int bpb = std::max(1, std::min(16, bpb_want));
-  int per_wave = lds_int2_per_wave(W, c->L, regs);
+  int per_wave = lds_int2_per_wave(W, c->L);
   while (bpb > 1 && (size_t)bpb * per_wave * sizeof(int2) > c->max_lds) --bpb;
   if ((size_t)per_wave * sizeof(int2) > c->max_lds) return fail(c, LOB_ECAP, "LDS window does not fit");
   g->W = W;
@@ -97,15 +91,22 @@ lob_status geometry(lob_ctx *c, int window, int cap_limit, int bpb_want, Geometr
   return LOB_OK;
 }
 
+// One matching launch over books of capacity <= cap_limit: the register kernel when
+// the plan allows it and every such book fits in registers, else the LDS kernel.
 lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bpb, hipStream_t s) {
   if (a.n == 0) return LOB_OK;
+  if (c->plan.registers && cap_limit <= lob::small_book_slots()) {
+    a.bpb = std::max(1, std::min(16, bpb));
+    hipError_t e = lob::launch_process_small(a, s);
+    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+  }
   Geometry g;
   lob_status st = geometry(c, window, cap_limit, bpb, &g);
   if (st != LOB_OK) return st;
   a.W = g.W;
   a.bpb = g.bpb;
   a.lds_int2_per_wave = g.per_wave;
-  hipError_t e = c->plan.registers ? lob::launch_process_reg(a, g.spill, s) : lob::launch_process(a, g.spill, s);
+  hipError_t e = lob::launch_process(a, g.spill, s);
   return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
 }
 
@@ -214,16 +215,15 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_ragged_done, hipEventDisableTiming);
   if (e == hipSuccess) {  // advisory on this platform
     (void)lob::set_process_lds_limit(c->max_lds);
-    (void)lob::set_process_reg_lds_limit(c->max_lds);
   }
   if (e != hipSuccess) {
     g_create_error = std::string("context setup: ") + hipGetErrorString(e);
     free_ctx(c);
     return LOB_EDEVICE;
   }
-  // default plan: each side's first 128 orders in registers, the rest of the book
-  // in LDS when it fits comfortably, otherwise a 256-slot window with the rest in
-  // HBM; four books per workgroup; ragged calls in one launch, longest stream first
+  // default plan: books of capacity <= 128 wholly in registers; larger books in LDS
+  // when they fit comfortably, otherwise a 256-slot window with the rest in HBM;
+  // four books per workgroup; ragged calls in one launch, longest stream first
   c->plan.lds_slots = c->max_cap <= 1024 ? c->max_cap : 256;
   c->plan.books_per_block = 4;
   c->plan.ragged_split = 0;
@@ -261,7 +261,7 @@ lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan) {
     return fail(ctx, LOB_EINVAL, "books_per_block_big");
   if (plan->registers != 0 && plan->registers != 1) return fail(ctx, LOB_EINVAL, "registers");
   for (int w : {plan->lds_slots, plan->lds_slots_big, plan->ragged_split > 0 ? plan->ragged_split : 1})
-    if ((size_t)lds_int2_per_wave(std::min(w, ctx->max_cap), ctx->L, plan->registers != 0) * sizeof(int2) >
+    if ((size_t)lds_int2_per_wave(std::min(w, ctx->max_cap), ctx->L) * sizeof(int2) >
         ctx->max_lds)
       return fail(ctx, LOB_ECAP, "LDS window does not fit in LDS");
   ctx->plan = *plan;

@@ -24,10 +24,9 @@ hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *i
                               int32_t *out, int64_t max_records, int64_t *counts, int64_t *offsets,
                               hipStream_t s);
 hipError_t launch_selftest(int32_t *out, hipStream_t s);
-hipError_t launch_process_reg(const ProcArgs &a, bool spill, hipStream_t s);
-hipError_t set_process_reg_lds_limit(size_t bytes);
+hipError_t launch_process_small(const ProcArgs &a, hipStream_t s);
 hipError_t launch_selftest_shift(int32_t *out, hipStream_t s);
-int regbook_slots();
+int small_book_slots();
 }  // namespace lob
 
 static_assert(sizeof(lob_book_status) == 96, "lob_book_status layout");

@@ -1,6 +1,6 @@
 // lob_device.h -- wavefront primitives and per-book state shared by the matching
-// kernels (lob_kernels.hip: book sides in LDS; lob_regbook.hip: the top of each
-// side in registers).
+// kernels (lob_kernels.hip: book sides in LDS; lob_small.hip: books of capacity
+// <= 128 wholly in registers).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -1,0 +1,648 @@
+// lob_small.hip -- matching kernel for books of capacity <= 128 orders per side.
+//
+// Same algorithm and results as lob_kernels.hip (one wavefront per book, each side
+// kept in price-time priority, slot 0 = best), different residency: while the
+// book's messages run, the whole book lives in VGPRs.  Side s is two 64-lane
+// chunks (slot 64c + lane in chunk c) of six registers each, one per order field
+// (P, Q, OID, TID, Ts, Tns of Section 4).  The best order is lane 0 of chunk 0;
+// changing one order is a lane-select; moving orders by one slot is a DPP wave
+// shift (wave_shr:1 / wave_shl:1) with the neighbouring chunk's edge lane carried
+// in, and chunk 1 is left alone while the side holds at most 64 orders; removing
+// several leading orders at once is a ds_bpermute.  Trade records are staged one
+// per lane (lane k holds the k-th pending record) and stored to the log 64 at a
+// time, so a message that trades once costs six lane-selects and no store.
+//
+// Per 64 messages the lanes decode the message cases, check that times do not
+// decrease and sum the submitted limit / market quantity; the scalar path per
+// message only dispatches on the case.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include "lob_device.h"
+#include "lob_internal.h"
+
+namespace lob {
+namespace {
+
+using namespace dev;
+
+constexpr int kSlots = 2 * kWave;  // orders per side the kernel holds
+
+// x with lane `lane` (uniform) replaced by the uniform value v
+__device__ __forceinline__ int wl(int x, int v, int lane) { return lane_id() == lane ? v : x; }
+
+// One chunk: the six fields of slots 64c + lane.
+struct Chunk {
+  int p, q, o, t, ts, tns;
+};
+
+struct Side {
+  Chunk c0, c1;
+};
+
+struct Book {
+  Side ask, bid;  // side 0 = asks, side 1 = bids
+};
+
+template <int SD>
+__device__ __forceinline__ Side &side(Book &b) {
+  if constexpr (SD == 0)
+    return b.ask;
+  else
+    return b.bid;
+}
+
+// Pending trade records, one per lane; k of them (uniform) are pending.
+struct Stage {
+  int p, q, po, ao, ts, tns;
+  int k;
+};
+
+__device__ __forceinline__ void flush(State &st, Stage &sg) {
+  if (sg.k == 0) return;
+  if (st.log) {
+    const long long room = st.log_cap - st.log_count;
+    const int stored = room < sg.k ? (room > 0 ? (int)room : 0) : sg.k;
+    const int l = lane_id();
+    if (l < stored) {
+      int2 *r = reinterpret_cast<int2 *>(st.log + (st.log_count + l) * kTradeFields);
+      r[0] = make_int2(sg.p, sg.q);
+      r[1] = make_int2(sg.po, sg.ao);
+      r[2] = make_int2(sg.ts, sg.tns);
+    }
+    if (stored < sg.k) st.flags |= kFlagTradeFull;
+    st.log_count += stored;
+  }
+  sg.k = 0;
+}
+
+// One trade from uniform values.
+__device__ __forceinline__ void stage_one(State &st, Stage &sg, int P, int fill, int po, int ao, int ts, int tns) {
+  sg.p = wl(sg.p, P, sg.k);
+  sg.q = wl(sg.q, fill, sg.k);
+  sg.po = wl(sg.po, po, sg.k);
+  sg.ao = wl(sg.ao, ao, sg.k);
+  sg.ts = wl(sg.ts, ts, sg.k);
+  sg.tns = wl(sg.tns, tns, sg.k);
+  if (++sg.k == kWave) flush(st, sg);
+}
+
+// ntr trades held by lanes [0, ntr) (P, fill, passive id per lane; the aggressor
+// fields are uniform): rotate them behind the pending ones.
+__device__ __forceinline__ void stage_many(State &st, Stage &sg, int ntr, int P, int fill, int po, int ao, int ts,
+                                           int tns) {
+  const int l = lane_id();
+  const int src = (l - sg.k) & 63;
+  const int rp = from_lane(P, src), rq = from_lane(fill, src), ro = from_lane(po, src);
+  const bool mine = l >= sg.k;
+  sg.p = mine ? rp : sg.p;
+  sg.q = mine ? rq : sg.q;
+  sg.po = mine ? ro : sg.po;
+  sg.ao = mine ? ao : sg.ao;
+  sg.ts = mine ? ts : sg.ts;
+  sg.tns = mine ? tns : sg.tns;
+  const int end = sg.k + ntr;
+  if (end >= kWave) {
+    sg.k = kWave;
+    flush(st, sg);
+    sg.p = rp;
+    sg.q = rq;
+    sg.po = ro;
+    sg.ao = ao;
+    sg.ts = ts;
+    sg.tns = tns;
+    sg.k = end - kWave;
+  } else {
+    sg.k = end;
+  }
+}
+
+// Agent fills (step form): trades where either side carries the agent's trader id.
+__device__ __forceinline__ void fills_one(State &st, int P, int fill, int po, int ao, int ts, int tns, int ptid,
+                                          int atid) {
+  if (!st.fills || (ptid != st.agent_tid && atid != st.agent_tid)) return;
+  if (st.fill_count < st.fill_cap && lane_id() == 0) {
+    int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)st.fill_count * kTradeFields);
+    r[0] = make_int2(P, fill);
+    r[1] = make_int2(po, ao);
+    r[2] = make_int2(ts, tns);
+  }
+  st.fill_count++;
+}
+
+__device__ __forceinline__ void fills_many(State &st, bool takes, int P, int fill, int po, int ao, int ts, int tns,
+                                           int ptid, int atid) {
+  if (!st.fills) return;
+  const bool ag = takes && (ptid == st.agent_tid || atid == st.agent_tid);
+  const uint64_t ma = ballot(ag);
+  if (ma == 0) return;
+  const int k = st.fill_count + popc(ma & mask_lt());
+  if (ag && k < st.fill_cap) {
+    int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)k * kTradeFields);
+    r[0] = make_int2(P, fill);
+    r[1] = make_int2(po, ao);
+    r[2] = make_int2(ts, tns);
+  }
+  st.fill_count += popc(ma);
+}
+
+__device__ __forceinline__ Chunk edge(const Chunk &x, int lane) {  // uniform fields of one lane
+  Chunk v;
+  v.p = rdlane(x.p, lane);
+  v.q = rdlane(x.q, lane);
+  v.o = rdlane(x.o, lane);
+  v.t = rdlane(x.t, lane);
+  v.ts = rdlane(x.ts, lane);
+  v.tns = rdlane(x.tns, lane);
+  return v;
+}
+
+// lanes with keep: x; others: x of the next lane (lane 63 takes `in`).  The shifted
+// values are computed by every lane before the select: a DPP move inside a
+// divergent branch would read inactive source lanes.
+__device__ __forceinline__ void pull_down(Chunk &x, bool keep, const Chunk &in) {
+  const int p = shl1(x.p, in.p), q = shl1(x.q, in.q), o = shl1(x.o, in.o), t = shl1(x.t, in.t);
+  const int ts = shl1(x.ts, in.ts), tns = shl1(x.tns, in.tns);
+  x.p = keep ? x.p : p;
+  x.q = keep ? x.q : q;
+  x.o = keep ? x.o : o;
+  x.t = keep ? x.t : t;
+  x.ts = keep ? x.ts : ts;
+  x.tns = keep ? x.tns : tns;
+}
+
+// Slots (k, n) of a side move down by one (slot k is dropped).
+__device__ __forceinline__ void remove_at(Side &S, int k, int n) {
+  const int l = lane_id();
+  if (n > kWave) {
+    const Chunk in = edge(S.c1, 0);
+    pull_down(S.c1, l + kWave < k, in);
+    pull_down(S.c0, l < k, in);
+  } else {
+    pull_down(S.c0, l < k, S.c0);
+  }
+}
+
+// lanes below pos: x; lane pos: v; lanes above: x of the previous lane (lane 0
+// takes `in`); shifted values computed by every lane first, as in pull_down.
+__device__ __forceinline__ void push_up(Chunk &x, bool keep, bool at, const Chunk &v, const Chunk &in) {
+  const int p = shr1(x.p, in.p), q = shr1(x.q, in.q), o = shr1(x.o, in.o), t = shr1(x.t, in.t);
+  const int ts = shr1(x.ts, in.ts), tns = shr1(x.tns, in.tns);
+  x.p = keep ? x.p : (at ? v.p : p);
+  x.q = keep ? x.q : (at ? v.q : q);
+  x.o = keep ? x.o : (at ? v.o : o);
+  x.t = keep ? x.t : (at ? v.t : t);
+  x.ts = keep ? x.ts : (at ? v.ts : ts);
+  x.tns = keep ? x.tns : (at ? v.tns : tns);
+}
+
+// The first m slots of a side (m >= 1) are removed: slot s takes slot s + m.
+__device__ __forceinline__ void remove_front(Side &S, int m, int n) {
+  if (m == 1) {
+    remove_at(S, 0, n);
+    return;
+  }
+  if (m >= n) return;  // the side is empty now
+  const int l = lane_id();
+  const int src = (l + m) & 63;
+  if (n <= kWave) {
+    S.c0.p = from_lane(S.c0.p, src);
+    S.c0.q = from_lane(S.c0.q, src);
+    S.c0.o = from_lane(S.c0.o, src);
+    S.c0.t = from_lane(S.c0.t, src);
+    S.c0.ts = from_lane(S.c0.ts, src);
+    S.c0.tns = from_lane(S.c0.tns, src);
+    return;
+  }
+  Chunk a, b;
+  a.p = from_lane(S.c0.p, src);
+  a.q = from_lane(S.c0.q, src);
+  a.o = from_lane(S.c0.o, src);
+  a.t = from_lane(S.c0.t, src);
+  a.ts = from_lane(S.c0.ts, src);
+  a.tns = from_lane(S.c0.tns, src);
+  b.p = from_lane(S.c1.p, src);
+  b.q = from_lane(S.c1.q, src);
+  b.o = from_lane(S.c1.o, src);
+  b.t = from_lane(S.c1.t, src);
+  b.ts = from_lane(S.c1.ts, src);
+  b.tns = from_lane(S.c1.tns, src);
+  if (m < kWave) {
+    const bool low = l + m < kWave;  // the source slot is in the same chunk
+    S.c0.p = low ? a.p : b.p;
+    S.c0.q = low ? a.q : b.q;
+    S.c0.o = low ? a.o : b.o;
+    S.c0.t = low ? a.t : b.t;
+    S.c0.ts = low ? a.ts : b.ts;
+    S.c0.tns = low ? a.tns : b.tns;
+    S.c1 = b;
+  } else {
+    S.c0 = b;  // slot l takes slot 64 + (l + m - 64)
+  }
+}
+
+// Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
+// with limit price lim and quantity q.  Returns the unfilled quantity.
+template <int OPP>
+__device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, int q, int a_oid, int a_tid, int ts,
+                                     int tns) {
+  Side &S = side<OPP>(bk);
+  const int n = st.n[OPP];
+  constexpr bool buyer = (OPP == 0);
+  if (q <= 0 || n == 0) return q;
+  const int bp = rdlane(S.c0.p, 0);
+  if (buyer ? bp > lim : bp < lim) return q;  // the best standing price does not overlap
+  const int bq = rdlane(S.c0.q, 0);
+  if (q <= bq) {
+    // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
+    const int bo = rdlane(S.c0.o, 0);
+    stage_one(st, sg, bp, q, bo, a_oid, ts, tns);
+    if (st.fills) fills_one(st, bp, q, bo, a_oid, ts, tns, rdlane(S.c0.t, 0), a_tid);
+    st.traded_qty += q;
+    st.n_trades++;
+    if (q < bq) {
+      S.c0.q = wl(S.c0.q, bq - q, 0);
+    } else {
+      remove_at(S, 0, n);
+      st.n[OPP] = n - 1;
+    }
+    return 0;
+  }
+  // the aggressor outlasts the best order: one prefix scan per chunk of crossing orders
+  const int l = lane_id();
+  int removed = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (c == 1 && (removed < kWave || n <= kWave || q == 0)) break;
+    Chunk &F = c == 0 ? S.c0 : S.c1;
+    const bool valid = c * kWave + l < n;
+    const bool cross = valid && (buyer ? F.p <= lim : F.p >= lim);
+    const int qv = cross ? F.q : 0;
+    const int incl = scan_incl(qv);
+    const int excl = incl - qv;
+    const bool takes = cross && excl < q;
+    const uint64_t mt = ballot(takes);
+    if (mt == 0) break;
+    const int ntr = popc(mt);
+    const bool full = cross && incl <= q;
+    const int nfull = popc(ballot(full));
+    const int fill = takes ? min(qv, q - excl) : 0;
+    stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
+    fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
+    F.q = (takes && !full) ? F.q - fill : F.q;  // the partially filled order, if any
+    const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
+    st.traded_qty += consumed;
+    st.n_trades += ntr;
+    q -= consumed;
+    removed += nfull;
+    if (nfull < kWave) break;
+  }
+  if (removed > 0) {
+    remove_front(S, removed, n);
+    st.n[OPP] = n - removed;
+  }
+  return q;
+}
+
+// Add (Section 4.1, item 1) on side SD: the new order goes behind every order with
+// an equal or better price, i.e. at its price-time position.
+template <int SD>
+__device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oid, int tid, int ts, int tns) {
+  Side &S = side<SD>(bk);
+  const int l = lane_id();
+  const int n = st.n[SD];
+  if (n >= st.cap) {
+    st.rejected_qty += Q;
+    st.flags |= kFlagSideFull;
+    return;
+  }
+  int pos = popc(ballot(l < n && (SD == 1 ? S.c0.p >= P : S.c0.p <= P)));
+  if (pos == kWave && n > kWave) pos += popc(ballot(l + kWave < n && (SD == 1 ? S.c1.p >= P : S.c1.p <= P)));
+  Chunk v;
+  v.p = P;
+  v.q = Q;
+  v.o = oid;
+  v.t = tid;
+  v.ts = ts;
+  v.tns = tns;
+  if (n >= kWave) {  // chunk 1 changes: slot 63 moves into slot 64, or the new order lands there
+    const Chunk in = edge(S.c0, 63);
+    push_up(S.c1, l + kWave < pos, l + kWave == pos, v, in);
+  }
+  push_up(S.c0, l < pos, l == pos, v, v);
+  st.n[SD] = n + 1;
+}
+
+// Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders) on side SD.
+template <int SD>
+__device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, int price) {
+  if (qty <= 0) return;
+  Side &S = side<SD>(bk);
+  const int l = lane_id();
+  const int n = st.n[SD];
+  int k = -1;
+  uint64_t m = ballot(l < n && S.c0.o == oid);
+  if (m) {
+    k = first_set(m);
+  } else if (n > kWave) {
+    m = ballot(l + kWave < n && S.c1.o == oid);
+    if (m) k = kWave + first_set(m);
+  }
+  if (k < 0) {
+    m = ballot(l < n && S.c0.o <= -9000 && S.c0.p == price);
+    if (m) {
+      k = first_set(m);
+    } else if (n > kWave) {
+      m = ballot(l + kWave < n && S.c1.o <= -9000 && S.c1.p == price);
+      if (m) k = kWave + first_set(m);
+    }
+  }
+  if (k < 0) {
+    st.cancel_miss++;
+    return;
+  }
+  const bool lo = k < kWave;
+  const int kl = k & 63;
+  const int Q = lo ? rdlane(S.c0.q, kl) : rdlane(S.c1.q, kl);
+  st.cancelled_qty += min(qty, Q);
+  const int left = Q - qty;
+  if (left > 0) {
+    if (lo)
+      S.c0.q = wl(S.c0.q, left, kl);
+    else
+      S.c1.q = wl(S.c1.q, left, kl);
+  } else {
+    remove_at(S, k, n);
+    st.n[SD] = n - 1;
+  }
+}
+
+// L2 of one side: the first L distinct prices with their summed quantities into
+// out[0..L) as (price, qty); missing levels (-1, 0).  A level is a run of equal
+// prices in priority order; its quantity is the running sum at its last order minus
+// the running sum at the previous level's last order.
+__device__ __forceinline__ void l2_side(const Side &S, int n, int L, int2 *out) {
+  const int l = lane_id();
+  int levels = 0, q_before = 0, end_before = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (c * kWave >= n) break;
+    const Chunk &F = c == 0 ? S.c0 : S.c1;
+    const int s = c * kWave + l;
+    const bool valid = s < n;
+    const int next_in = (c == 0 && n > kWave) ? rdlane(S.c1.p, 0) : 0;
+    const int next = shl1(F.p, next_in);
+    const bool is_last = valid && (s + 1 == n || next != F.p);
+    const int incl = q_before + scan_incl(valid ? F.q : 0);
+    const uint64_t ml = ballot(is_last);
+    const uint64_t below = ml & mask_lt();
+    const int src = below ? 63 - __builtin_clzll(below) : 0;
+    const int prev_end = from_lane(incl, src);
+    const int lev = levels + popc(below);
+    if (is_last && lev < L) out[lev] = make_int2(F.p, incl - (below ? prev_end : end_before));
+    if (ml) end_before = rdlane(incl, 63 - __builtin_clzll(ml));
+    levels += popc(ml);
+    q_before = rdlane(incl, 63);
+  }
+  const int have = levels < L ? levels : L;
+  if (l >= have && l < L) out[l] = make_int2(-1, 0);
+}
+
+__device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L, int32_t *row) {
+  int2 *o = reinterpret_cast<int2 *>(row);
+  l2_side(bk.ask, st.n[0], L, o);
+  l2_side(bk.bid, st.n[1], L, o + L);
+}
+
+// One message (Section 4.2) given its case code: 1/2 limit sell/buy, 3/4 market
+// sell/buy, 5/6 cancel-or-delete on the ask/bid side, 0 not processed.
+__device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, int P, int Q, int oid, int tid,
+                                            int ts, int tns) {
+  if (code == 0) return;
+  const bool buys = (code & 1) == 0;
+  if (code <= 4) {
+    // limit: match, then rest the remainder as one new order (item 1); market: match
+    // at price 0 (sell) / max_int (buy) and drop the rest (item 3)
+    const bool limit = code <= 2;
+    const int lim = limit ? P : (buys ? INT_MAX : 0);
+    const int rem = buys ? match<0>(bk, st, sg, lim, Q, oid, tid, ts, tns)
+                         : match<1>(bk, st, sg, lim, Q, oid, tid, ts, tns);
+    if (rem > 0) {
+      if (!limit)
+        st.market_discarded += rem;
+      else if (buys)
+        insert<1>(bk, st, P, rem, oid, tid, ts, tns);
+      else
+        insert<0>(bk, st, P, rem, oid, tid, ts, tns);
+    }
+  } else if (buys) {
+    cancel<1>(bk, st, oid, Q, P);
+  } else {
+    cancel<0>(bk, st, oid, Q, P);
+  }
+}
+
+// Sum over the wave of a non-negative int32 per lane, as 64-bit.
+__device__ __forceinline__ long long wave_sum(int v) {
+  const int lo = scan_incl(v & 0xffff);
+  const int hi = scan_incl((int)((unsigned)v >> 16));
+  return (long long)rdlane(lo, 63) + ((long long)rdlane(hi, 63) << 16);
+}
+
+// The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
+// form's agent orders) msgs2[beg2, beg2 + n2), in 64-message chunks.
+__device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, const ProcArgs &a, long long beg1,
+                                            long long n1, long long beg2, long long n2, bool l2_each) {
+  const int l = lane_id();
+  const long long total = n1 + n2;
+#pragma nounroll
+  for (long long k0 = 0; k0 < total; k0 += kWave) {
+    const int cnt = (int)((total - k0) < kWave ? (total - k0) : kWave);
+    int4 u = make_int4(0, 0, 0, 0), v = make_int4(0, 0, 0, 0);
+    if (l < cnt) {
+      const long long k = k0 + l;
+      const int32_t *rec = k < n1 ? a.msgs + (beg1 + k) * kMsgFields : a.msgs2 + (beg2 + k - n1) * kMsgFields;
+      const int4 *mp = reinterpret_cast<const int4 *>(rec);
+      u = mp[0];
+      v = mp[1];
+    }
+    const int T = u.x, S = u.y;
+    const bool ok = l < cnt && T >= 1 && T <= 4 && (S == 1 || S == -1);
+    const int code = !ok ? 0 : (T == 1 ? 1 : T == 4 ? 3 : 5) + (S == 1 ? 1 : 0);
+    const uint64_t vmask = ballot(ok);
+    if (vmask) {
+      // times of valid messages must not decrease: compare with the previous valid
+      // lane, or with the last valid time before this chunk
+      const uint64_t below = vmask & mask_lt();
+      const int src = below ? 63 - __builtin_clzll(below) : 0;
+      const int pts = from_lane(v.z, src), ptns = from_lane(v.w, src);
+      const bool has_prev = below != 0 || st.seen;
+      const int cts = below ? pts : st.last_ts, ctns = below ? ptns : st.last_tns;
+      const bool dec = ok && has_prev && (v.z < cts || (v.z == cts && v.w < ctns));
+      if (ballot(dec)) st.flags |= kFlagTimeOrder;
+      const int top = 63 - __builtin_clzll(vmask);
+      st.last_ts = rdlane(v.z, top);
+      st.last_tns = rdlane(v.w, top);
+      st.seen = 1;
+      // submitted quantity of limit and market orders (Q > 0 only)
+      st.limit_qty += wave_sum((code == 1 || code == 2) && u.w > 0 ? u.w : 0);
+      st.market_qty += wave_sum((code == 3 || code == 4) && u.w > 0 ? u.w : 0);
+    }
+    st.n_msgs += cnt;
+#pragma nounroll
+    for (int j = 0; j < cnt; ++j) {
+      const int c = rdlane(code, j);
+      process_msg(bk, st, sg, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
+                  rdlane(v.w, j));
+      if (l2_each && k0 + j < n1) write_l2(bk, st, a.levels, a.l2_out + (beg1 + k0 + j) * 4 * a.levels);
+    }
+  }
+}
+
+__device__ __forceinline__ void load_chunk(Chunk &x, const int2 *base, int cap, int s, int n) {
+  if (s < n) {
+    const int2 pq = base[s], ot = base[cap + s], tt = base[2 * cap + s];
+    x.p = pq.x;
+    x.q = pq.y;
+    x.o = ot.x;
+    x.t = ot.y;
+    x.ts = tt.x;
+    x.tns = tt.y;
+  } else {
+    x.p = x.q = x.o = x.t = x.ts = x.tns = 0;
+  }
+}
+
+__device__ __forceinline__ void store_chunk(const Chunk &x, int2 *base, int cap, int s, int n) {
+  if (s < n) {
+    base[s] = make_int2(x.p, x.q);
+    base[cap + s] = make_int2(x.o, x.t);
+    base[2 * cap + s] = make_int2(x.ts, x.tns);
+  }
+}
+
+__device__ void run_book(const ProcArgs &a, int i) {
+  const int l = lane_id();
+  const int book = a.book_ids ? uni(a.book_ids[i]) : i;
+  if (book < 0 || book >= a.n_total) return;
+  BookHdr *h = a.hdr + book;
+  State st;
+  st.n[0] = uni(h->n[0]);
+  st.n[1] = uni(h->n[1]);
+  st.cap = uni(h->cap);
+  if (st.cap > kSlots) {  // not launched for such books; leave the book untouched
+    if (l == 0) h->flags |= kFlagBadLoad;
+    return;
+  }
+  st.flags = uni(h->flags);
+  st.n_msgs = uni64(h->n_msgs);
+  st.n_trades = uni64(h->n_trades);
+  st.limit_qty = uni64(h->limit_qty);
+  st.market_qty = uni64(h->market_qty);
+  st.traded_qty = uni64(h->traded_qty);
+  st.cancelled_qty = uni64(h->cancelled_qty);
+  st.market_discarded = uni64(h->market_discarded);
+  st.rejected_qty = uni64(h->rejected_qty);
+  st.cancel_miss = uni64(h->cancel_miss);
+  st.last_ts = uni(h->last_ts);
+  st.last_tns = uni(h->last_tns);
+  st.seen = uni(h->seen_time);
+  st.log_cap = uni64(h->log_cap);
+  st.log_count = uni64(h->log_count);
+  st.log = a.log ? a.log + uni64(h->log_off) * kTradeFields : nullptr;
+  const int row = a.out_rows ? uni(a.out_rows[i]) : i;  // output row of this book
+  st.fills = a.fills ? a.fills + (int64_t)row * a.fill_cap * kTradeFields : nullptr;
+  st.fill_cap = a.fill_cap;
+  st.fill_count = 0;
+  st.agent_tid = a.agent_tid;
+
+  int2 *hb = a.books + uni64(h->book_off);
+  const int cap = st.cap;
+  Book bk;
+  load_chunk(bk.ask.c0, hb, cap, l, st.n[0]);
+  load_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0]);
+  load_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1]);
+  load_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1]);
+  Stage sg;
+  sg.p = sg.q = sg.po = sg.ao = sg.ts = sg.tns = 0;
+  sg.k = 0;
+
+  long long beg1 = 0, n1 = 0;
+  if (a.msgs) {
+    if (a.ranges) {
+      beg1 = a.ranges[2 * i];
+      n1 = a.ranges[2 * i + 1] - beg1;
+    } else if (a.offs) {
+      beg1 = a.offs[i];
+      n1 = a.offs[i + 1] - beg1;
+    } else {
+      beg1 = (long long)i * a.w1;
+      n1 = a.w1;
+    }
+  }
+  const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
+  process_all(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, a.l2_mode == 1);
+  flush(st, sg);
+  if (a.l2_mode == 2) write_l2(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
+
+  store_chunk(bk.ask.c0, hb, cap, l, st.n[0]);
+  store_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0]);
+  store_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1]);
+  store_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1]);
+  if (st.fills) {
+    if (st.fill_count > st.fill_cap) st.flags |= kFlagFillsFull;
+    if (l == 0 && a.fill_counts) a.fill_counts[row] = st.fill_count;
+  }
+  if (l == 0) {
+    h->n[0] = st.n[0];
+    h->n[1] = st.n[1];
+    h->flags = st.flags;
+    h->n_msgs = st.n_msgs;
+    h->n_trades = st.n_trades;
+    h->limit_qty = st.limit_qty;
+    h->market_qty = st.market_qty;
+    h->traded_qty = st.traded_qty;
+    h->cancelled_qty = st.cancelled_qty;
+    h->market_discarded = st.market_discarded;
+    h->rejected_qty = st.rejected_qty;
+    h->cancel_miss = st.cancel_miss;
+    h->last_ts = st.last_ts;
+    h->last_tns = st.last_tns;
+    h->seen_time = st.seen;
+    h->log_count = st.log_count;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_process_small(ProcArgs a) {
+  const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
+  const int i = blockIdx.x * a.bpb + w;
+  if (i >= a.n) return;
+  run_book(a, i);
+}
+
+__global__ void k_selftest_shift(int32_t *out) {
+  const int l = lane_id();
+  const int x = 3 * l + 1;
+  out[l] = shr1(x, -5);        // lane l-1; lane 0 gets the fill
+  out[64 + l] = shl1(x, -7);   // lane l+1; lane 63 gets the fill
+  out[128 + l] = from_lane(x, (l + 5) & 63);
+}
+
+}  // namespace
+
+int small_book_slots() { return kSlots; }
+
+hipError_t launch_process_small(const ProcArgs &a, hipStream_t s) {
+  const int threads = a.bpb * kWave;
+  const int grid = (a.n + a.bpb - 1) / a.bpb;
+  hipLaunchKernelGGL(k_process_small, dim3(grid), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_selftest_shift(int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_selftest_shift, dim3(1), dim3(64), 0, s, out);
+  return hipGetLastError();
+}
+
+}  // namespace lob
