@@ -41,12 +41,25 @@ def host_cores():
     return max(1, min(16, n))
 
 
+KERNEL_SOURCES = ("paper_2308_13289_amd/csrc/lob_kernels.hip", "paper_2308_13289_amd/csrc/lob_small.hip",
+                  "paper_2308_13289_amd/csrc/lob_device.h", "paper_2308_13289_amd/csrc/lob_internal.h",
+                  "paper_2308_13289_amd/build.py")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for p in ("paper_2308_13289_amd/csrc/lob_kernels.hip", "paper_2308_13289_amd/csrc/lob_internal.h"):
+    for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def kernel_name(ctx, w):
+    """The matching kernel a plain launch over these books runs (same rule as liblob)."""
+    plan = ctx.get_plan()
+    if plan.registers and int(w.caps.max()) <= 128:
+        return "k_process_small"
+    return "k_process<true>" if int(w.caps.max()) > plan.lds_slots else "k_process<false>"
 
 
 def load_traffic(name, khash):
@@ -144,7 +157,8 @@ def bench_uniform(args, w, desc):
     kavg = float(np.mean(kern_ms)) / 1e3
     achieved = alg_bytes / kavg / 1e9
     khash = kernel_source_hash()
-    traffic = load_traffic(f"k_process_{args.workload}", khash)
+    wl = "c1" if args.workload in ("all", "c1") else args.workload
+    traffic = load_traffic(f"{kernel_name(ctx, w)}_{wl}", khash)
     res = {
         "metric": METRIC, "value": n_msgs * args.steps / wall, "unit": "msgs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -158,7 +172,7 @@ def bench_uniform(args, w, desc):
                       "max": float(np.max(kern_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "kernel": "k_process<false>",
+                     "alg_bytes_per_launch": alg_bytes, "kernel": kernel_name(ctx, w),
                      "kernel_hash": khash},
         "h2d_s": h2d_s,
         "pcie_inclusive_msgs_per_s": n_msgs / (h2d_s + wall / args.steps),
@@ -404,6 +418,87 @@ def bench_step(args, n_books=8192, n_steps=1000, window=100, fills_cap=32):
     return res
 
 
+# the paper's own timings (RTX 2080 Ti, JAX; Tables 1-4), quoted as context
+PAPER_MS = {
+    "single_book": {10: {"add": 0.115, "cancel": 0.081, "match": 0.184},
+                    100: {"add": 0.117, "cancel": 0.095, "match": 0.206},
+                    1000: {"add": 0.162, "cancel": 0.093, "match": 0.243}},
+    "market_qty": {0: 0.132, 10: 0.206, 500: 0.271, 1000: 0.336, 10000: 2.326},
+    "thousand_books": {10: {"add": 1.402, "cancel": 1.407, "match": 1.393},
+                       100: {"add": 2.649, "cancel": 2.614, "match": 2.612},
+                       1000: {"add": 11.75, "cancel": 11.43, "match": 11.47}},
+}
+
+
+def _stats(ms):
+    ms = np.asarray(ms)
+    return {"mean_ms": float(ms.mean()), "p50_ms": float(np.percentile(ms, 50)),
+            "p99_ms": float(np.percentile(ms, 99))}
+
+
+def bench_micro(args, trials=1000, trials_many=100, n_books=1000):
+    """The paper's per-operation timings on this library: a book of capacity N in
+    {10, 100, 1000} filled to one third per side, then one message -- add (limit, no
+    cross), cancel, match (limit across the spread), or a market order of size Q_a
+    (N = 100) -- to one book (single_book, market_qty) or the same message to 1000
+    identical books in one call (thousand_books).  Every trial restores the book
+    first (reset + write_book, untimed); HIP events bracket the one process call."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {"single_book": {}, "market_qty": {}, "thousand_books": {}, "trials": trials,
+           "trials_thousand_books": trials_many, "paper_2080ti_ms": PAPER_MS}
+    for N in (10, 100, 1000):
+        seeds, _ = W.micro_book(N)
+        ctx = lob.Context(np.full(n_books, N, np.int32), l2_levels=LEVELS, trade_log_records=2 * N + 64)
+        if args.plan:
+            ctx.set_plan(**json.loads(args.plan))
+        d_seeds = torch.from_numpy(np.tile(seeds, (n_books, 1))).to(dev)
+        d_soffs = torch.arange(n_books + 1, dtype=torch.int64, device=dev) * len(seeds)
+        ctx.process(d_seeds, d_soffs, stream=stream)
+        dump = ctx.read_book(N, stream=stream)
+        one = torch.zeros(1, dtype=torch.int32, device=dev)
+        off1 = torch.tensor([0, 1], dtype=torch.int64, device=dev)
+        offs_all = torch.arange(n_books + 1, dtype=torch.int64, device=dev)
+        cases = [(op, None) for op in W.MICRO_OPS]
+        if N == 100:
+            cases += [("market", q) for q in (0, 10, 500, 1000, 10000)]
+        out["single_book"][N] = {}
+        out["thousand_books"][N] = {}
+        for op, q in cases:
+            msgs = W.micro_messages(N, op, trials, market_qty=q)
+            d_msgs = torch.from_numpy(msgs).to(dev)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(trials)]
+            for t in range(trials):
+                ctx.reset(book_ids=one, stream=stream)
+                ctx.write_book(dump[:1], book_ids=one, stream=stream)
+                ev[t][0].record(stream)
+                ctx.process(d_msgs[t:t + 1], off1, book_ids=one, stream=stream)
+                ev[t][1].record(stream)
+            torch.cuda.synchronize()
+            st = _stats([a.elapsed_time(b) for a, b in ev])
+            if op == "market":
+                out["market_qty"][q] = st
+                continue
+            out["single_book"][N][op] = st
+            d_many = torch.from_numpy(np.repeat(msgs[:trials_many], n_books, axis=0)).to(dev)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(trials_many)]
+            for t in range(trials_many):
+                ctx.reset(stream=stream)
+                ctx.write_book(dump, stream=stream)
+                ev[t][0].record(stream)
+                ctx.process(d_many[t * n_books:(t + 1) * n_books], offs_all, stream=stream)
+                ev[t][1].record(stream)
+            torch.cuda.synchronize()
+            st = _stats([a.elapsed_time(b) for a, b in ev])
+            st["per_book_us"] = st["mean_ms"] * 1e3 / n_books
+            out["thousand_books"][N][op] = st
+        out["plan_N%d" % N] = ctx.get_plan().as_dict()
+        ctx.close()
+    return out
+
+
 def bench_copy(args, nbytes=1 << 30):
     """Calibration for HBM byte counters: one device-to-device copy of a known size
     (reads nbytes, writes nbytes)."""
@@ -424,7 +519,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3", "c4", "copy"])
+    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro"])
     ap.add_argument("--tune-trials", type=int, default=16)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
@@ -450,6 +545,9 @@ def main():
     if args.workload == "copy":
         print(json.dumps(bench_copy(args)), flush=True)
         return
+    if args.workload == "micro":
+        print(json.dumps(bench_micro(args)), flush=True)
+        return
     t0 = time.perf_counter()
     if args.workload in ("c1", "all"):
         w = W.c1(threads=host_cores())
@@ -472,6 +570,9 @@ def main():
         log(f"step form: {res['step_form']['steps_per_s']:.0f} steps/s, "
             f"p99 {res['step_form']['eager_step_ms']['p99']:.3f} ms")
         res["serving"] = bench_serving(args)
+        res["paper_tables"] = bench_micro(args, trials=200, trials_many=50)
+        log("paper tables: single-book add/cancel/match at N=100: " + ", ".join(
+            f"{res['paper_tables']['single_book'][100][op]['mean_ms'] * 1e3:.1f} us" for op in W.MICRO_OPS))
     print(json.dumps(res), flush=True)
 
 

@@ -249,11 +249,12 @@ lob_status lob_write_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books
 lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, void *stream);
 
 /* Diagnostic: run the wavefront primitives the matcher is built on on one
- * wavefront and write 384 int32 results to out (device), with x = 3*lane + 1:
+ * wavefront and write 576 int32 results to out (device), with x = 3*lane + 1:
  * [0,64) inclusive prefix sums of (lane % 7 + 1); [64,128) number of lanes <=
  * lane with lane % 3 == 0; [128,192) number of lanes below lane; [192,256) x of
  * lane-1 (lane 0: -5); [256,320) x of lane+1 (lane 63: -7); [320,384) x of lane
- * (lane+5) % 64. */
+ * (lane+5) % 64; [384,448) x of lane-1 (lane 0: 0); [448,512) x of lane+1
+ * (lane 63: 0); [512,576) x with lane 17 replaced by -9. */
 lob_status lob_selftest(int32_t device, int32_t *out, void *stream);
 
 /* ---------------------------------------------------------------- serving */

@@ -26,6 +26,9 @@ def command(out):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             # no packed fp32 instructions anywhere (the matcher is integer-only anyway)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # the matchers branch on wave-uniform values: keep those branches as
+            # scalar branches instead of structurizing them into exec-masked flow
+            "-mllvm", "-structurizecfg-skip-uniform-regions=true",
             "-Wall", "-Wno-unused-function",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             SOURCES[0], SOURCES[1], "-x", "hip", SOURCES[2], SOURCES[3], "-o", out]

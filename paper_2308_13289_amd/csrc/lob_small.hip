@@ -22,6 +22,10 @@
 #include "lob_device.h"
 #include "lob_internal.h"
 
+// v_writelane_b32 through its LLVM intrinsic (clang has no builtin for it here), so
+// the compiler still sees the instruction and inserts its wait states.
+__device__ int lob_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace lob {
 namespace {
 
@@ -30,7 +34,10 @@ using namespace dev;
 constexpr int kSlots = 2 * kWave;  // orders per side the kernel holds
 
 // x with lane `lane` (uniform) replaced by the uniform value v
-__device__ __forceinline__ int wl(int x, int v, int lane) { return lane_id() == lane ? v : x; }
+__device__ __forceinline__ int wl(int x, int v, int lane) { return lob_writelane_i32(v, lane, x); }
+// lane l receives lane l-1 (up1) or l+1 (dn1); the lane without a source receives 0
+__device__ __forceinline__ int up1(int x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dn1(int x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xf, 0xf, true); }
 
 // One chunk: the six fields of slots 64c + lane.
 struct Chunk {
@@ -134,7 +141,7 @@ __device__ __forceinline__ void fills_one(State &st, int P, int fill, int po, in
 __device__ __forceinline__ void fills_many(State &st, bool takes, int P, int fill, int po, int ao, int ts, int tns,
                                            int ptid, int atid) {
   if (!st.fills) return;
-  const bool ag = takes && (ptid == st.agent_tid || atid == st.agent_tid);
+  const bool ag = takes & ((ptid == st.agent_tid) | (atid == st.agent_tid));
   const uint64_t ma = ballot(ag);
   if (ma == 0) return;
   const int k = st.fill_count + popc(ma & mask_lt());
@@ -145,6 +152,11 @@ __device__ __forceinline__ void fills_many(State &st, bool takes, int P, int fil
     r[2] = make_int2(ts, tns);
   }
   st.fill_count += popc(ma);
+}
+
+// lanes [0, k) as a mask, k uniform (k <= 0: none, k >= 64: all)
+__device__ __forceinline__ uint64_t lanes_below(int k) {
+  return k >= kWave ? ~0ull : (k <= 0 ? 0ull : (1ull << k) - 1ull);
 }
 
 __device__ __forceinline__ Chunk edge(const Chunk &x, int lane) {  // uniform fields of one lane
@@ -158,43 +170,52 @@ __device__ __forceinline__ Chunk edge(const Chunk &x, int lane) {  // uniform fi
   return v;
 }
 
-// lanes with keep: x; others: x of the next lane (lane 63 takes `in`).  The shifted
-// values are computed by every lane before the select: a DPP move inside a
+// Lanes with `take` receive the next lane's order (dn) or the previous lane's (up).
+// Every lane computes the moved value before the select: a DPP move inside a
 // divergent branch would read inactive source lanes.
-__device__ __forceinline__ void pull_down(Chunk &x, bool keep, const Chunk &in) {
-  const int p = shl1(x.p, in.p), q = shl1(x.q, in.q), o = shl1(x.o, in.o), t = shl1(x.t, in.t);
-  const int ts = shl1(x.ts, in.ts), tns = shl1(x.tns, in.tns);
-  x.p = keep ? x.p : p;
-  x.q = keep ? x.q : q;
-  x.o = keep ? x.o : o;
-  x.t = keep ? x.t : t;
-  x.ts = keep ? x.ts : ts;
-  x.tns = keep ? x.tns : tns;
+__device__ __forceinline__ void shift_dn(Chunk &x, bool take) {
+  const int p = dn1(x.p), q = dn1(x.q), o = dn1(x.o), t = dn1(x.t), ts = dn1(x.ts), tns = dn1(x.tns);
+  x.p = take ? p : x.p;
+  x.q = take ? q : x.q;
+  x.o = take ? o : x.o;
+  x.t = take ? t : x.t;
+  x.ts = take ? ts : x.ts;
+  x.tns = take ? tns : x.tns;
+}
+
+__device__ __forceinline__ void shift_up(Chunk &x, bool take) {
+  const int p = up1(x.p), q = up1(x.q), o = up1(x.o), t = up1(x.t), ts = up1(x.ts), tns = up1(x.tns);
+  x.p = take ? p : x.p;
+  x.q = take ? q : x.q;
+  x.o = take ? o : x.o;
+  x.t = take ? t : x.t;
+  x.ts = take ? ts : x.ts;
+  x.tns = take ? tns : x.tns;
+}
+
+// lane `lane` of x takes the uniform order v
+__device__ __forceinline__ void put(Chunk &x, const Chunk &v, int lane) {
+  x.p = wl(x.p, v.p, lane);
+  x.q = wl(x.q, v.q, lane);
+  x.o = wl(x.o, v.o, lane);
+  x.t = wl(x.t, v.t, lane);
+  x.ts = wl(x.ts, v.ts, lane);
+  x.tns = wl(x.tns, v.tns, lane);
 }
 
 // Slots (k, n) of a side move down by one (slot k is dropped).
 __device__ __forceinline__ void remove_at(Side &S, int k, int n) {
   const int l = lane_id();
   if (n > kWave) {
-    const Chunk in = edge(S.c1, 0);
-    pull_down(S.c1, l + kWave < k, in);
-    pull_down(S.c0, l < k, in);
+    const Chunk in = edge(S.c1, 0);  // slot 64 moves to slot 63
+    shift_dn(S.c1, l + kWave >= k);
+    if (k < kWave) {
+      shift_dn(S.c0, l >= k);
+      put(S.c0, in, 63);
+    }
   } else {
-    pull_down(S.c0, l < k, S.c0);
+    shift_dn(S.c0, l >= k);
   }
-}
-
-// lanes below pos: x; lane pos: v; lanes above: x of the previous lane (lane 0
-// takes `in`); shifted values computed by every lane first, as in pull_down.
-__device__ __forceinline__ void push_up(Chunk &x, bool keep, bool at, const Chunk &v, const Chunk &in) {
-  const int p = shr1(x.p, in.p), q = shr1(x.q, in.q), o = shr1(x.o, in.o), t = shr1(x.t, in.t);
-  const int ts = shr1(x.ts, in.ts), tns = shr1(x.tns, in.tns);
-  x.p = keep ? x.p : (at ? v.p : p);
-  x.q = keep ? x.q : (at ? v.q : q);
-  x.o = keep ? x.o : (at ? v.o : o);
-  x.t = keep ? x.t : (at ? v.t : t);
-  x.ts = keep ? x.ts : (at ? v.ts : ts);
-  x.tns = keep ? x.tns : (at ? v.tns : tns);
 }
 
 // The first m slots of a side (m >= 1) are removed: slot s takes slot s + m.
@@ -277,20 +298,20 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
     if (c == 1 && (removed < kWave || n <= kWave || q == 0)) break;
     Chunk &F = c == 0 ? S.c0 : S.c1;
     const bool valid = c * kWave + l < n;
-    const bool cross = valid && (buyer ? F.p <= lim : F.p >= lim);
+    const bool cross = valid & (buyer ? F.p <= lim : F.p >= lim);
     const int qv = cross ? F.q : 0;
     const int incl = scan_incl(qv);
     const int excl = incl - qv;
-    const bool takes = cross && excl < q;
+    const bool takes = cross & (excl < q);
     const uint64_t mt = ballot(takes);
     if (mt == 0) break;
     const int ntr = popc(mt);
-    const bool full = cross && incl <= q;
+    const bool full = cross & (incl <= q);
     const int nfull = popc(ballot(full));
     const int fill = takes ? min(qv, q - excl) : 0;
     stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
     fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
-    F.q = (takes && !full) ? F.q - fill : F.q;  // the partially filled order, if any
+    F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
     const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
     st.traded_qty += consumed;
     st.n_trades += ntr;
@@ -317,8 +338,8 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
     st.flags |= kFlagSideFull;
     return;
   }
-  int pos = popc(ballot(l < n && (SD == 1 ? S.c0.p >= P : S.c0.p <= P)));
-  if (pos == kWave && n > kWave) pos += popc(ballot(l + kWave < n && (SD == 1 ? S.c1.p >= P : S.c1.p <= P)));
+  int pos = popc(ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P) & lanes_below(n));
+  if (pos == kWave && n > kWave) pos += popc(ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P) & lanes_below(n - kWave));
   Chunk v;
   v.p = P;
   v.q = Q;
@@ -328,9 +349,15 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
   v.tns = tns;
   if (n >= kWave) {  // chunk 1 changes: slot 63 moves into slot 64, or the new order lands there
     const Chunk in = edge(S.c0, 63);
-    push_up(S.c1, l + kWave < pos, l + kWave == pos, v, in);
+    shift_up(S.c1, l + kWave > pos);
+    if (pos < kWave) put(S.c1, in, 0);
   }
-  push_up(S.c0, l < pos, l == pos, v, v);
+  if (pos < kWave) {
+    shift_up(S.c0, l > pos);
+    put(S.c0, v, pos);
+  } else {
+    put(S.c1, v, pos - kWave);
+  }
   st.n[SD] = n + 1;
 }
 
@@ -342,19 +369,19 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
   const int l = lane_id();
   const int n = st.n[SD];
   int k = -1;
-  uint64_t m = ballot(l < n && S.c0.o == oid);
+  uint64_t m = ballot(S.c0.o == oid) & lanes_below(n);
   if (m) {
     k = first_set(m);
   } else if (n > kWave) {
-    m = ballot(l + kWave < n && S.c1.o == oid);
+    m = ballot(S.c1.o == oid) & lanes_below(n - kWave);
     if (m) k = kWave + first_set(m);
   }
   if (k < 0) {
-    m = ballot(l < n && S.c0.o <= -9000 && S.c0.p == price);
+    m = ballot((S.c0.o <= -9000) & (S.c0.p == price)) & lanes_below(n);
     if (m) {
       k = first_set(m);
     } else if (n > kWave) {
-      m = ballot(l + kWave < n && S.c1.o <= -9000 && S.c1.p == price);
+      m = ballot((S.c1.o <= -9000) & (S.c1.p == price)) & lanes_below(n - kWave);
       if (m) k = kWave + first_set(m);
     }
   }
@@ -393,7 +420,7 @@ __device__ __forceinline__ void l2_side(const Side &S, int n, int L, int2 *out) 
     const bool valid = s < n;
     const int next_in = (c == 0 && n > kWave) ? rdlane(S.c1.p, 0) : 0;
     const int next = shl1(F.p, next_in);
-    const bool is_last = valid && (s + 1 == n || next != F.p);
+    const bool is_last = valid & ((s + 1 == n) | (next != F.p));
     const int incl = q_before + scan_incl(valid ? F.q : 0);
     const uint64_t ml = ballot(is_last);
     const uint64_t below = ml & mask_lt();
@@ -468,7 +495,7 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
       v = mp[1];
     }
     const int T = u.x, S = u.y;
-    const bool ok = l < cnt && T >= 1 && T <= 4 && (S == 1 || S == -1);
+    const bool ok = (l < cnt) & (T >= 1) & (T <= 4) & ((S == 1) | (S == -1));
     const int code = !ok ? 0 : (T == 1 ? 1 : T == 4 ? 3 : 5) + (S == 1 ? 1 : 0);
     const uint64_t vmask = ballot(ok);
     if (vmask) {
@@ -479,15 +506,16 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
       const int pts = from_lane(v.z, src), ptns = from_lane(v.w, src);
       const bool has_prev = below != 0 || st.seen;
       const int cts = below ? pts : st.last_ts, ctns = below ? ptns : st.last_tns;
-      const bool dec = ok && has_prev && (v.z < cts || (v.z == cts && v.w < ctns));
+      const bool dec = ok & has_prev & ((v.z < cts) | ((v.z == cts) & (v.w < ctns)));
       if (ballot(dec)) st.flags |= kFlagTimeOrder;
       const int top = 63 - __builtin_clzll(vmask);
       st.last_ts = rdlane(v.z, top);
       st.last_tns = rdlane(v.w, top);
       st.seen = 1;
       // submitted quantity of limit and market orders (Q > 0 only)
-      st.limit_qty += wave_sum((code == 1 || code == 2) && u.w > 0 ? u.w : 0);
-      st.market_qty += wave_sum((code == 3 || code == 4) && u.w > 0 ? u.w : 0);
+      const int qpos = u.w > 0 ? u.w : 0;
+      st.limit_qty += wave_sum(((code == 1) | (code == 2)) ? qpos : 0);
+      st.market_qty += wave_sum(((code == 3) | (code == 4)) ? qpos : 0);
     }
     st.n_msgs += cnt;
 #pragma nounroll
@@ -627,6 +655,9 @@ __global__ void k_selftest_shift(int32_t *out) {
   out[l] = shr1(x, -5);        // lane l-1; lane 0 gets the fill
   out[64 + l] = shl1(x, -7);   // lane l+1; lane 63 gets the fill
   out[128 + l] = from_lane(x, (l + 5) & 63);
+  out[192 + l] = up1(x);         // lane l-1; lane 0 gets 0
+  out[256 + l] = dn1(x);         // lane l+1; lane 63 gets 0
+  out[320 + l] = wl(x, -9, 17);  // lane 17 replaced
 }
 
 }  // namespace

@@ -122,7 +122,7 @@ def _stream(stream, device):
 
 
 def selftest(device=0):
-    out = torch.empty(384, dtype=torch.int32, device=f"cuda:{device}")
+    out = torch.empty(576, dtype=torch.int32, device=f"cuda:{device}")
     st = load().lob_selftest(device, _ptr(out), _stream(None, out.device))
     if st != OK:
         raise LobError(st, "selftest launch failed")

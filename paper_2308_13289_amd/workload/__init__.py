@@ -184,3 +184,84 @@ def requests(n_req, lam, n_books, seed=SEED, tag=TAGS["c4"]):
     lib().fg_requests(seed, tag, n_req, float(lam), n_books, _ptr(arr), _ptr(book), _ptr(kind),
                       _ptr(size))
     return arr, book, kind, size
+
+
+# ---------------------------------------------------------------- operation microbenchmarks
+# Inputs for the paper's per-operation timings (Section 4.1, Tables 1-4): a book of
+# capacity N filled to one third per side with random orders, and single messages
+# that add without crossing, cancel a resting order, cross the spread, or are market
+# orders of a given size.
+
+MICRO_OPS = ("add", "cancel", "match")
+MICRO_MID = 10_000_000
+
+
+def _micro_rng(cap, what, seed):
+    return np.random.Generator(np.random.PCG64([seed, 0x51C0, int(cap), int(what)]))
+
+
+def _qty(rng, n):
+    return np.minimum(1 + np.floor(rng.lognormal(4.0, 1.0, n)), 10_000).astype(np.int32)
+
+
+def micro_book(cap, seed=SEED, mid=MICRO_MID, tick=TICK):
+    """Seed messages filling a book of capacity `cap` to one third per side (at least
+    one order each): limit asks at mid + k*tick and bids at mid - k*tick with
+    k = 1 + Geometric(0.3), qty = 1 + floor(LogNormal(4, 1)) clipped to 10,000, order
+    ids 1, 2, ..., times (34199, i).  Returns [2*n][8] int32 and the per-order
+    (side, price, qty, oid) table of what rests after them."""
+    rng = _micro_rng(cap, 0, seed)
+    n = max(1, cap // 3)
+    k = rng.geometric(0.3, 2 * n)  # numpy's geometric counts trials: 1 + failures, >= 1
+    side = np.repeat(np.array([-1, 1], np.int32), n)
+    price = np.where(side == -1, mid + k * tick, mid - k * tick).astype(np.int32)
+    qty = _qty(rng, 2 * n)
+    oid = np.arange(1, 2 * n + 1, dtype=np.int32)
+    m = np.zeros((2 * n, 8), np.int32)
+    m[:, 0] = 1
+    m[:, 1] = side
+    m[:, 2] = price
+    m[:, 3] = qty
+    m[:, 4] = oid
+    m[:, 5] = 7
+    m[:, 6] = 34199
+    m[:, 7] = np.arange(2 * n, dtype=np.int32)
+    return m, np.stack([side, price, qty, oid], axis=1)
+
+
+def micro_messages(cap, op, n_trials, seed=SEED, mid=MICRO_MID, tick=TICK, market_qty=None):
+    """One message per trial, each applied to the freshly restored micro_book:
+      add     limit at mid -/+ tick*U{0..5} (buy/sell), never crossing the spread
+      cancel  partial-or-full cancel (qty ~ U[1, resting]) of a uniform resting order
+      match   limit crossing the spread: buy at mid + 1000*tick / sell at mid - 1000*tick
+      market  market order of quantity market_qty (side uniform)
+    Returns [n_trials][8] int32 with time (34200, trial)."""
+    what = {"add": 1, "cancel": 2, "match": 3, "market": 4}[op]
+    rng = _micro_rng(cap, 16 * what + (0 if market_qty is None else 1 + int(market_qty) % 7919), seed)
+    _, rest = micro_book(cap, seed=seed, mid=mid, tick=tick)
+    t = np.arange(n_trials)
+    m = np.zeros((n_trials, 8), np.int32)
+    side = np.where(rng.random(n_trials) < 0.5, 1, -1).astype(np.int32)
+    m[:, 4] = 1_000_000 + t
+    m[:, 5] = 8
+    m[:, 6] = 34200
+    m[:, 7] = t
+    if op == "add":
+        off = tick * rng.integers(0, 6, n_trials)
+        m[:, 0], m[:, 1] = 1, side
+        m[:, 2] = np.where(side == 1, mid - off, mid + off)
+        m[:, 3] = _qty(rng, n_trials)
+    elif op == "cancel":
+        pick = rest[rng.integers(0, rest.shape[0], n_trials)]
+        m[:, 0], m[:, 1], m[:, 2] = 2, pick[:, 0], pick[:, 1]
+        m[:, 3] = 1 + np.floor(rng.random(n_trials) * pick[:, 2]).astype(np.int32)
+        m[:, 4] = pick[:, 3]
+    elif op == "match":
+        m[:, 0], m[:, 1] = 1, side
+        m[:, 2] = np.where(side == 1, mid + 1000 * tick, mid - 1000 * tick)
+        m[:, 3] = _qty(rng, n_trials)
+    elif op == "market":
+        m[:, 0], m[:, 1] = 4, side
+        m[:, 2] = 0
+        m[:, 3] = int(market_qty)
+    return m

@@ -42,6 +42,9 @@ def test_selftest_primitives():
     np.testing.assert_array_equal(out[192:256], np.concatenate([[-5], x[:-1]]))
     np.testing.assert_array_equal(out[256:320], np.concatenate([x[1:], [-7]]))
     np.testing.assert_array_equal(out[320:384], x[(lanes + 5) % 64])
+    np.testing.assert_array_equal(out[384:448], np.concatenate([[0], x[:-1]]))
+    np.testing.assert_array_equal(out[448:512], np.concatenate([x[1:], [0]]))
+    np.testing.assert_array_equal(out[512:576], np.where(lanes == 17, -9, x))
 
 
 RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}}
