@@ -26,6 +26,11 @@
  *       Section 5.1.1 are never processed.  A side other than +1 / -1 is a no-op.
  *   R8  A limit or market message with Q <= 0 trades nothing and rests nothing,
  *       which is what add-then-clean-up gives (Table 2 uses Q_a = 0).
+ *   R9  Book initialisation from an L2 snapshot (Section 5.1.1): one order per
+ *       level with the level's summed quantity; the ids -9000, -9001, ... are
+ *       handed out level by level, ask before bid, the column order of a LOBSTER
+ *       order-book row.  The paper leaves trader id and time of these orders open:
+ *       both are arguments.  A snapshot that is not a valid book is refused.
  */
 #include "lob_oracle.h"
 
@@ -308,6 +313,58 @@ int32_t orc_dump(const orc_book *b, int32_t side, int32_t *out) {
   }
   free(taken);
   return n;
+}
+
+/* Section 5.1.1: the book at the start of a window comes from its L2 snapshot (R9). */
+int32_t orc_seed_l2(orc_book *b, const int32_t *l2, int32_t levels, int32_t tid, int32_t ts, int32_t tns) {
+  for (int32_t i = 0; i < b->N; ++i) {
+    set_empty(&b->A[i]);
+    set_empty(&b->B[i]);
+  }
+  memset(&b->st, 0, sizeof(b->st));
+  b->next_arrival = 0;
+  b->seen_time = 0;
+  b->last_ts = b->last_tns = 0;
+  /* is it a book?  strictly ordered prices per side, room for every level, not crossed */
+  int ok = 1;
+  int32_t best_px[2] = {0, 0};
+  for (int sd = 0; sd < 2; ++sd) {
+    int32_t count = 0, prev = 0;
+    for (int32_t l = 0; l < levels; ++l) {
+      const int32_t *e = l2 + ((size_t)sd * levels + l) * 2;
+      if (e[1] <= 0) continue;
+      if (count > 0 && (sd == 0 ? e[0] <= prev : e[0] >= prev)) ok = 0;
+      if (count == 0) best_px[sd] = e[0];
+      prev = e[0];
+      count++;
+    }
+    if (count > b->N) ok = 0;
+    if (count == 0) best_px[sd] = sd == 0 ? INT32_MAX : INT32_MIN;
+  }
+  if (best_px[1] >= best_px[0]) ok = 0;
+  if (!ok) {
+    b->st.flags |= ORC_FLAG_BAD_LOAD;
+    return -1;
+  }
+  int32_t oid = -9000, placed = 0;
+  for (int32_t l = 0; l < levels; ++l) {
+    for (int sd = 0; sd < 2; ++sd) {
+      const int32_t *e = l2 + ((size_t)sd * levels + l) * 2;
+      if (e[1] <= 0) continue;
+      order_t *own = sd == 1 ? b->B : b->A;
+      int32_t slot = 0;
+      while (!is_empty(&own[slot])) slot++; /* room was checked above */
+      own[slot].f[P] = e[0];
+      own[slot].f[Q] = e[1];
+      own[slot].f[OID] = oid--;
+      own[slot].f[TID] = tid;
+      own[slot].f[TS] = ts;
+      own[slot].f[TNS] = tns;
+      own[slot].arrival = b->next_arrival++;
+      placed++;
+    }
+  }
+  return placed;
 }
 
 /* ---------------------------------------------------------------- batch runner */

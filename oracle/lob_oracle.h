@@ -50,6 +50,7 @@ extern "C" {
 #define ORC_FLAG_SIDE_FULL 1   /* a limit remainder was rejected: its side was full */
 #define ORC_FLAG_TIME_ORDER 2  /* a message's time was earlier than the previous one */
 #define ORC_FLAG_TRADE_FULL 4  /* the caller's trade buffer for this book overflowed */
+#define ORC_FLAG_BAD_LOAD 16   /* an L2 snapshot handed to orc_seed_l2 was not a book */
 
 /* L2 snapshot modes of orc_run */
 #define ORC_L2_NONE 0
@@ -90,6 +91,17 @@ int32_t orc_dump(const orc_book *b, int32_t side, int32_t *out);
 
 void orc_get_stats(const orc_book *b, orc_stats *out);
 int32_t orc_capacity(const orc_book *b);
+
+/* Initialise a book from an L2 snapshot (Section 5.1.1): l2 = [2][levels][2], side
+ * 0 asks (best first, ascending prices), side 1 bids (best first, descending), each
+ * entry (price, qty); entries with qty <= 0 are missing levels.  The book is
+ * emptied and its counters cleared, then every present level becomes one order
+ * holding the level's quantity, with trader id `tid` and time (ts, tns).  Order ids
+ * start at -9000 and descend, level by level, ask before bid (R9).  A snapshot
+ * that is not a book -- prices not strictly ordered, bid >= ask, or more levels
+ * than the capacity on a side -- leaves the book empty, sets ORC_FLAG_BAD_LOAD and
+ * returns -1; otherwise returns the number of orders placed. */
+int32_t orc_seed_l2(orc_book *b, const int32_t *l2, int32_t levels, int32_t tid, int32_t ts, int32_t tns);
 
 /* Batch runner: books run independently on `n_threads` host threads.
  *   caps[n_books]            capacity per side of each book

@@ -20,7 +20,7 @@ BUILT = os.path.join(HERE, "liboracle.so")
 LIB = os.environ.get("LOB_ORACLE_LIB", BUILT)
 
 L2_NONE, L2_PER_MESSAGE, L2_FINAL = 0, 1, 2
-FLAG_SIDE_FULL, FLAG_TIME_ORDER, FLAG_TRADE_FULL = 1, 2, 4
+FLAG_SIDE_FULL, FLAG_TIME_ORDER, FLAG_TRADE_FULL, FLAG_BAD_LOAD = 1, 2, 4, 16
 
 
 class Stats(ctypes.Structure):
@@ -67,6 +67,8 @@ def lib():
         L.orc_dump.restype = ctypes.c_int32
         L.orc_dump.argtypes = [VP, ctypes.c_int32, P32]
         L.orc_get_stats.argtypes = [VP, ctypes.POINTER(Stats)]
+        L.orc_seed_l2.restype = ctypes.c_int32
+        L.orc_seed_l2.argtypes = [VP, P32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.orc_run.restype = ctypes.c_int32
         L.orc_run.argtypes = [ctypes.c_int32, P32, P32, P64, ctypes.c_int32, ctypes.c_int32, P32,
                               P32, P64, P64, P64, VP, P32, ctypes.c_int32, ctypes.c_int32]
@@ -101,6 +103,12 @@ class Book:
         m = np.ascontiguousarray(msg, dtype=np.int32)
         n = lib().orc_process(self._h, _p32(m), _p32(self._tr), self.cap)
         return self._tr[:n].copy()
+
+    def seed_l2(self, l2, tid=0, ts=0, tns=0):
+        """Empty the book and place one order per present level of an L2 snapshot
+        [2][levels][2]; returns the orders placed, or -1 if it is not a book."""
+        a = np.ascontiguousarray(l2, dtype=np.int32)
+        return int(lib().orc_seed_l2(self._h, _p32(a), int(a.shape[1]), int(tid), int(ts), int(tns)))
 
     def l2(self, levels=10):
         out = np.zeros((2, levels, 2), np.int32)

@@ -34,10 +34,14 @@ MUTANTS = [
     ("remainder_not_added", "if (rem > 0) add(b, buys, m, rem); /* R8 */", "(void)rem;"),
     ("l2_wrong_sum", "if (!is_empty(&side[i]) && side[i].f[P] == px) qsum += side[i].f[Q];",
      "if (!is_empty(&side[i]) && side[i].f[P] == px) qsum = side[i].f[Q];"),
+    ("seed_ids_side_by_side", "for (int32_t l = 0; l < levels; ++l) {\n    for (int sd = 0; sd < 2; ++sd) {",
+     "for (int sd = 0; sd < 2; ++sd) {\n    for (int32_t l = 0; l < levels; ++l) {"),
+    ("seed_accepts_locked_book", "if (best_px[1] >= best_px[0]) ok = 0;", "if (best_px[1] > best_px[0]) ok = 0;"),
+    ("seed_ids_ascending", "own[slot].f[OID] = oid--;", "own[slot].f[OID] = oid++;"),
 ]
 
 PIN_TESTS = ["tests/test_oracle_golden.py", "tests/test_oracle_bruteforce.py::test_random_sequences",
-             "tests/test_oracle_invariants.py"]
+             "tests/test_oracle_invariants.py", "tests/test_oracle_seed.py"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
