@@ -83,6 +83,9 @@ typedef int32_t lob_status;
 #define LOB_BOOK_TIME_ORDER 2   /* a message's time was earlier than the last one */
 #define LOB_BOOK_TRADE_FULL 4   /* trades were dropped: the book's trade log full */
 #define LOB_BOOK_FILLS_FULL 8   /* agent fills were dropped: the fills buffer full */
+#define LOB_BOOK_BAD_LOAD 16    /* lob_write_book rows out of priority order or past
+                                   the capacity, or lob_seed_l2 given a snapshot
+                                   that is not a book                             */
 
 typedef struct {
   int32_t n_books;                       /* books in the context, >= 1             */
@@ -248,6 +251,22 @@ lob_status lob_write_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books
 /* Empty the listed books, their trade logs and their counters. */
 lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, void *stream);
 
+/* Start each listed book from an L2 snapshot, as JAX-LOB starts an episode window
+ * (Section 5.1.1).  l2 is device [n_books][2][levels][2] in lob_read_l2's layout:
+ * side 0 asks best first (ascending prices), side 1 bids best first (descending),
+ * entries (price, qty), qty <= 0 = missing level; levels in 1..LOB_MAX_LEVELS.
+ * Each book is emptied together with its counters and trade log, then every
+ * present level becomes ONE order holding the level's quantity (the snapshot does
+ * not tell the orders of a level apart): order ids -9000, -9001, ... handed out
+ * level by level with the ask before the bid (the column order of a LOBSTER
+ * order-book row), trader id init_tid, time times[i] = (Ts, Tns) (device
+ * [n_books][2], NULL = (0, 0)).  Such orders are what the cancel rule for initial
+ * orders (id <= -9000, matched by price) acts on.  A snapshot that is not a book
+ * -- prices not strictly ordered on a side, best bid >= best ask, or more levels
+ * on a side than the capacity -- leaves the book empty with LOB_BOOK_BAD_LOAD. */
+lob_status lob_seed_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *l2, int32_t levels,
+                       const int32_t *times, int32_t init_tid, void *stream);
+
 /* Diagnostic: run the wavefront primitives the matcher is built on on one
  * wavefront and write 576 int32 results to out (device), with x = 3*lane + 1:
  * [0,64) inclusive prefix sums of (lane % 7 + 1); [64,128) number of lanes <=
@@ -256,6 +275,26 @@ lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, voi
  * (lane+5) % 64; [384,448) x of lane-1 (lane 0: 0); [448,512) x of lane+1
  * (lane 63: 0); [512,576) x with lane 17 replaced by -9. */
 lob_status lob_selftest(int32_t device, int32_t *out, void *stream);
+
+/* ---------------------------------------------------------------- replay windows */
+
+/* Windowed replay data (Section 5.1.1, data loading).  Host memory only, no GPU
+ * work.  One book's stream msgs_host[n_msgs][8], times not decreasing, is cut into
+ * n_windows consecutive windows of window_s seconds, window k holding the
+ * messages with start_s + k*window_s <= Ts < start_s + (k+1)*window_s (messages
+ * before start_s or past the last window are in none), and each window into steps
+ * of msgs_per_step messages.  out_host [n_windows][max_steps][msgs_per_step][8]
+ * (or NULL: only count) receives each window's messages in order, the rest of its
+ * last step and the steps after it all-zero (type 0: the step form never
+ * processes them); steps_host[k] = steps of window k that hold messages (the
+ * episode of that window ends after them); first_host[k] = index of window k's
+ * first message, first_host[n_windows] = one past the last window's messages.
+ * Returns LOB_ECAP when a window needs more than max_steps steps (it is cut off
+ * at max_steps and steps_host says max_steps; call with out_host = NULL to size),
+ * LOB_EINVAL for bad sizes or a time that goes back across a window boundary. */
+lob_status lob_windows(const int32_t *msgs_host, int64_t n_msgs, int32_t start_s, int32_t window_s,
+                       int32_t msgs_per_step, int32_t max_steps, int32_t n_windows, int32_t *out_host,
+                       int32_t *steps_host, int64_t *first_host);
 
 /* ---------------------------------------------------------------- serving */
 

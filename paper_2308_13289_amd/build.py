@@ -8,7 +8,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblob.so")
 SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_small.hip"),
-           os.path.join(CSRC, "lob_api.cpp"), os.path.join(CSRC, "lob_serve.cpp")]
+           os.path.join(CSRC, "lob_api.cpp"), os.path.join(CSRC, "lob_serve.cpp"),
+           os.path.join(CSRC, "lob_windows.cpp")]
 HEADERS = [os.path.join(CSRC, "lob_internal.h"), os.path.join(CSRC, "lob_ctx.h"),
            os.path.join(CSRC, "lob_device.h"),
            os.path.join(ROOT, "include", "lob.h")]
@@ -31,7 +32,7 @@ def command(out):
             "-mllvm", "-structurizecfg-skip-uniform-regions=true",
             "-Wall", "-Wno-unused-function",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-            SOURCES[0], SOURCES[1], "-x", "hip", SOURCES[2], SOURCES[3], "-o", out]
+            SOURCES[0], SOURCES[1], "-x", "hip", SOURCES[2], SOURCES[3], "-x", "c++", SOURCES[4], "-o", out]
 
 
 def up_to_date():

@@ -602,6 +602,19 @@ lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, voi
   return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "reset");
 }
 
+lob_status lob_seed_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *l2, int32_t levels,
+                       const int32_t *times, int32_t init_tid, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (levels < 1 || levels > LOB_MAX_LEVELS) return fail(ctx, LOB_EINVAL, "levels out of range");
+  if (n_books == 0) return LOB_OK;
+  if (!l2) return fail(ctx, LOB_EINVAL, "l2 is null");
+  DeviceGuard g(ctx->device);
+  hipError_t e = lob::launch_seed_l2(ctx->d_hdr, ctx->d_books, book_ids, n_books, ctx->n_books, levels, l2, times,
+                                     init_tid, (hipStream_t)stream);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "seed_l2");
+}
+
 lob_status lob_selftest(int32_t device, int32_t *out, void *stream) {
   if (!out) return LOB_EINVAL;
   DeviceGuard g(device);

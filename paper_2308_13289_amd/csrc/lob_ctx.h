@@ -24,6 +24,8 @@ hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *i
                               int32_t *out, int64_t max_records, int64_t *counts, int64_t *offsets,
                               hipStream_t s);
 hipError_t launch_selftest(int32_t *out, hipStream_t s);
+hipError_t launch_seed_l2(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
+                          const int32_t *l2, const int32_t *times, int tid, hipStream_t s);
 hipError_t launch_process_small(const ProcArgs &a, hipStream_t s);
 hipError_t launch_selftest_shift(int32_t *out, hipStream_t s);
 int small_book_slots();

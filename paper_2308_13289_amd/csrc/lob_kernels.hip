@@ -670,6 +670,70 @@ __global__ void __launch_bounds__(256) k_write_book(BookHdr *hdr, int2 *books, c
   if (l == 0 && bad) h->flags |= kFlagBadLoad;
 }
 
+// Book initialisation from an L2 snapshot (Section 5.1.1): one wave per book, lane
+// l holds level l of both sides.  The book is emptied with its counters and log;
+// a snapshot that is a book (strictly ordered prices, not crossed, fits the
+// capacity) becomes one order per present level (qty > 0), ids -9000, -9001, ...
+// level by level with the ask before the bid; otherwise the book stays empty and
+// is flagged.
+__global__ void __launch_bounds__(256) k_seed_l2(BookHdr *hdr, int2 *books, const int32_t *ids, int n,
+                                                  int n_total, int L, const int32_t *l2, const int32_t *times,
+                                                  int tid) {
+  const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
+  const int i = blockIdx.x * 4 + w;
+  if (i >= n) return;
+  const int l = lane_id();
+  const int bid = ids ? uni(ids[i]) : i;
+  if (bid < 0 || bid >= n_total) return;
+  BookHdr *h = hdr + bid;
+  const int cap = uni(h->cap);
+  int2 *bk = books + uni64(h->book_off);
+  const int2 *row = reinterpret_cast<const int2 *>(l2) + (int64_t)i * 2 * L;  // [2][L] (price, qty)
+  int2 e[2];
+  uint64_t mp[2];
+  int cnt[2], best[2];
+  bool bad = false;
+  for (int sd = 0; sd < 2; ++sd) {
+    e[sd] = l < L ? row[sd * L + l] : make_int2(0, 0);
+    const bool pres = (l < L) & (e[sd].y > 0);
+    mp[sd] = ballot(pres);
+    cnt[sd] = popc(mp[sd]);
+    // strictly ordered: each present level against the previous present one
+    const uint64_t below = mp[sd] & mask_lt();
+    const int src = below ? 63 - __builtin_clzll(below) : 0;
+    const int prev = from_lane(e[sd].x, src);
+    const bool unordered = pres & (below != 0) & (sd == 0 ? e[sd].x <= prev : e[sd].x >= prev);
+    if (ballot(unordered) || cnt[sd] > cap) bad = true;
+    best[sd] = mp[sd] ? rdlane(e[sd].x, first_set(mp[sd])) : 0;
+  }
+  if (cnt[0] > 0 && cnt[1] > 0 && best[1] >= best[0]) bad = true;
+  const int ts = times ? uni(times[2 * i]) : 0, tns = times ? uni(times[2 * i + 1]) : 0;
+  if (!bad) {
+    // rank in the order ask 0, bid 0, ask 1, bid 1, ...
+    const int before = popc(mp[0] & mask_lt()) + popc(mp[1] & mask_lt());
+    for (int sd = 0; sd < 2; ++sd) {
+      const bool pres = (mp[sd] >> l) & 1;
+      if (pres) {
+        const int slot = popc(mp[sd] & mask_lt());
+        const int oid = -9000 - before - (sd == 1 && ((mp[0] >> l) & 1) ? 1 : 0);
+        bk[(sd * 3 + 0) * cap + slot] = make_int2(e[sd].x, e[sd].y);
+        bk[(sd * 3 + 1) * cap + slot] = make_int2(oid, tid);
+        bk[(sd * 3 + 2) * cap + slot] = make_int2(ts, tns);
+      }
+    }
+  }
+  if (l == 0) {
+    h->n[0] = bad ? 0 : cnt[0];
+    h->n[1] = bad ? 0 : cnt[1];
+    h->flags = bad ? kFlagBadLoad : 0;
+    h->log_count = 0;
+    h->n_msgs = h->n_trades = h->limit_qty = h->market_qty = h->traded_qty = h->cancelled_qty = 0;
+    h->market_discarded = h->rejected_qty = h->cancel_miss = 0;
+    h->last_ts = h->last_tns = 0;
+    h->seen_time = 0;
+  }
+}
+
 // Trade-log drain, pass 1 (one block): counts and exclusive offsets.
 __global__ void __launch_bounds__(1024) k_trade_counts(const BookHdr *hdr, const int32_t *ids, int n,
                                                         int n_total, int64_t *counts, int64_t *offsets) {
@@ -789,6 +853,12 @@ hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *i
   if (e != hipSuccess || n == 0) return e;
   hipLaunchKernelGGL(k_trade_copy, dim3(n), dim3(256), 0, s, hdr, log, ids, n, n_total, counts, offsets,
                      max_records, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_l2(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
+                          const int32_t *l2, const int32_t *times, int tid, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_l2, dim3((n + 3) / 4), dim3(256), 0, s, hdr, books, ids, n, n_total, L, l2, times, tid);
   return hipGetLastError();
 }
 

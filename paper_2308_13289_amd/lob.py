@@ -51,7 +51,7 @@ class Plan(ctypes.Structure):
 _lib = None
 EXPORTS = ["lob_create", "lob_destroy", "lob_last_error", "lob_info", "lob_set_plan", "lob_get_plan",
            "lob_process_messages", "lob_process_ragged", "lob_autotune_ragged", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
-           "lob_read_book", "lob_write_book", "lob_reset", "lob_selftest"]
+           "lob_read_book", "lob_write_book", "lob_reset", "lob_seed_l2", "lob_selftest", "lob_windows"]
 
 
 def load(path=None):
@@ -97,6 +97,10 @@ def load(path=None):
     L.lob_write_book.argtypes = [vp, vp, i32, vp, i32, vp]
     L.lob_reset.restype = i32
     L.lob_reset.argtypes = [vp, vp, i32, vp]
+    L.lob_windows.restype = i32
+    L.lob_windows.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, vp]
+    L.lob_seed_l2.restype = i32
+    L.lob_seed_l2.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp]
     L.lob_selftest.restype = i32
     L.lob_selftest.argtypes = [i32, vp, vp]
     if path is None:
@@ -119,6 +123,23 @@ def _ptr(t, dtype=None, name="tensor"):
 def _stream(stream, device):
     s = stream if stream is not None else torch.cuda.current_stream(device)
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def windows(msgs, start_s, window_s, msgs_per_step, max_steps, n_windows):
+    """Windowed replay data of one book's stream (host numpy [n][8] int32): returns
+    (windows [n_windows][max_steps][msgs_per_step][8], steps [n_windows],
+    first [n_windows + 1]).  Raises LobError if a window needs more steps."""
+    m = np.ascontiguousarray(msgs, dtype=np.int32).reshape(-1, 8)
+    out = np.zeros((n_windows, max_steps, msgs_per_step, 8), np.int32)
+    steps = np.zeros(n_windows, np.int32)
+    first = np.zeros(n_windows + 1, np.int64)
+    st = load().lob_windows(m.ctypes.data if len(m) else None, len(m), int(start_s), int(window_s),
+                            int(msgs_per_step), int(max_steps), int(n_windows), out.ctypes.data,
+                            steps.ctypes.data, first.ctypes.data)
+    if st != OK:
+        raise LobError(st, "lob_windows: " + ("a window needs more than max_steps steps" if st == ECAP
+                                              else "bad arguments or times out of order"))
+    return out, steps, first
 
 
 def selftest(device=0):
@@ -285,3 +306,11 @@ class Context:
     def reset(self, book_ids=None, stream=None):
         ids, n = self._ids(book_ids, None)
         self._check(self._lib.lob_reset(self._h, ids, n, _stream(stream, self.device)))
+
+    def seed_l2(self, l2, times=None, init_tid=0, book_ids=None, stream=None):
+        """Start books from L2 snapshots l2[n][2][levels][2] (device int32); times[n][2]
+        device int32 or None."""
+        ids, n = self._ids(book_ids, l2.shape[0])
+        self._check(self._lib.lob_seed_l2(self._h, ids, n, _ptr(l2, torch.int32, "l2"), int(l2.shape[2]),
+                                          _ptr(times, torch.int32, "times"), int(init_tid),
+                                          _stream(stream, self.device)))
