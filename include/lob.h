@@ -276,6 +276,72 @@ lob_status lob_seed_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, c
  * (lane 63: 0); [512,576) x with lane 17 replaced by -9. */
 lob_status lob_selftest(int32_t device, int32_t *out, void *stream);
 
+/* ---------------------------------------------------------------- execution environment */
+
+/* Per-book state of an execution task (Section 5.2), device memory, one per listed
+ * book; lob_exec_step reads and updates it.  The caller fills it at the episode
+ * start (exec_qty = revenue = done = flags = 0). */
+typedef struct {
+  int32_t task_side;  /* +1: buy task_qty shares; -1: sell them                      */
+  int32_t task_qty;   /* Q_task                                                      */
+  int32_t exec_qty;   /* Q_exec: agent quantity executed so far, at most Q_task (upd.) */
+  int32_t done;       /* 1 once Q_exec = Q_task or the episode time is over (upd.)   */
+  int64_t revenue;    /* sum of P_j * Q_j over the counted agent fills (updated)     */
+  int32_t p_init;     /* P_init: mid price at the episode start                      */
+  int32_t start_s;    /* episode start time (Ts, Tns)                                */
+  int32_t start_ns;
+  int32_t end_s;      /* episode end (s); from end_s - 60 on, the remaining quantity
+                         is submitted as one market order instead of the action     */
+  int32_t next_oid;   /* order id of the agent's next order (updated)                */
+  int32_t flags;      /* LOB_EXEC_* (updated)                                        */
+} lob_exec_state;     /* 48 bytes */
+
+#define LOB_EXEC_TRADES_MISSING 1 /* the trade log had no room for some of a step's
+                                     trades: that step's VWAP misses them          */
+
+typedef struct {
+  int32_t tick;          /* tick size in price units                                 */
+  int32_t passive_ticks; /* n of the passive price                                   */
+  int32_t agent_tid;     /* trader id carried by the agent's orders                  */
+  int32_t keep_trades;   /* 0: the step's trades leave the trade log once the reward
+                            is computed; 1: they stay for lob_read_trades           */
+  double lambda;         /* weight of the drift term of the reward                   */
+} lob_exec_params;
+
+/* One step of the execution environment of Section 5.2 per listed book, three
+ * kernels on `stream`, allocating nothing:
+ *  1. the action -- sizes action_qty[i][0..4) at the far-touch, mid, near-touch and
+ *     passive prices of the book as it stands (buy task: ask, floor((ask+bid)/2),
+ *     bid, bid - passive_ticks*tick; sell task: bid, mid, ask, ask + passive_ticks*
+ *     tick) -- becomes up to four limit orders (size <= 0, or a reference price
+ *     missing or <= 0: no order), ids state.next_oid, next_oid+1, ..., trader id
+ *     agent_tid, time of the step's last data message.  From end_s - 60 on, one
+ *     market order for Q_task - Q_exec replaces them; a done task sends nothing.
+ *  2. the W data messages of window[i] then those orders run through the matcher
+ *     (lob_step's semantics; the trades are logged for step 3).
+ *  3. obs[i] (6W + 8 int32): best bid prices after each data message [W], best ask
+ *     prices [W], mid prices floor((ask+bid)/2) [W], passive prices [W], spreads
+ *     ask - bid [W], level-1 imbalances Q_ask - Q_bid [W] (a missing best price
+ *     reads -1; mid, passive and spread read -1 when a price they need is
+ *     missing; a missing side's quantity is 0), then the current time (Ts, Tns) =
+ *     the step's last data message, the elapsed time (Ts, Tns) since the episode
+ *     start, P_init, the drift P_mid - P_init (P_mid of the last data message; 0
+ *     if missing), Q_task and Q_exec.  reward[i] (float64) =
+ *       sum_j Q_j (P_j - P_VWAP) + lambda * sum_j Q_j (P_VWAP - P_init),
+ *     P_VWAP = sum_i Q_i P_i / sum_i Q_i over all trades of the step, j over the
+ *     agent's fills of the step with Q_j capped so that Q_exec never exceeds
+ *     Q_task (0 when the step made no trade); computed from exact int64 sums in
+ *     that order with no fused operations.  The agent's fills go to
+ *     agent_fills[i] / agent_fill_counts[i] as in lob_step; state is updated.
+ * W in 1..256; the trade log of a book needs room for the step's trades (2 per
+ * message at most), else LOB_EXEC_TRADES_MISSING.  window [n][W][8], action_qty
+ * [n][4], state [n], obs [n][6W+8], reward [n], agent_fills [n][F][6] with F >= 1,
+ * agent_fill_counts [n]; all device memory, obs 4-byte aligned. */
+lob_status lob_exec_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window,
+                         int32_t W, const int32_t *action_qty, const lob_exec_params *params,
+                         lob_exec_state *state, int32_t *obs, double *reward, int32_t *agent_fills, int32_t F,
+                         int32_t *agent_fill_counts, void *stream);
+
 /* ---------------------------------------------------------------- replay windows */
 
 /* Windowed replay data (Section 5.1.1, data loading).  Host memory only, no GPU

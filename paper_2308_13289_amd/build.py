@@ -8,6 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblob.so")
 SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_small.hip"),
+           os.path.join(CSRC, "lob_exec.hip"),
            os.path.join(CSRC, "lob_api.cpp"), os.path.join(CSRC, "lob_serve.cpp"),
            os.path.join(CSRC, "lob_windows.cpp")]
 HEADERS = [os.path.join(CSRC, "lob_internal.h"), os.path.join(CSRC, "lob_ctx.h"),
@@ -30,9 +31,12 @@ def command(out):
             # the matchers branch on wave-uniform values: keep those branches as
             # scalar branches instead of structurizing them into exec-masked flow
             "-mllvm", "-structurizecfg-skip-uniform-regions=true",
+            # the execution reward is float64 arithmetic in a fixed order: no fused ops
+            "-ffp-contract=off",
             "-Wall", "-Wno-unused-function",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-            SOURCES[0], SOURCES[1], "-x", "hip", SOURCES[2], SOURCES[3], "-x", "c++", SOURCES[4], "-o", out]
+            SOURCES[0], SOURCES[1], SOURCES[2], "-x", "hip", SOURCES[3], SOURCES[4], "-x", "c++", SOURCES[5],
+            "-o", out]
 
 
 def up_to_date():

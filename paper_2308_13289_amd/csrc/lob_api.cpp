@@ -50,6 +50,8 @@ void free_ctx(lob_ctx *c) {
   (void)hipFree(c->d_books);
   (void)hipFree(c->d_log);
   (void)hipFree(c->d_stage);
+  (void)hipFree(c->d_exec_acts);
+  (void)hipFree(c->d_exec_aux);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->ev_staged) (void)hipEventDestroy(c->ev_staged);
   if (c->ev_ragged_done) (void)hipEventDestroy(c->ev_ragged_done);
@@ -201,6 +203,8 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
             alloc((void **)&c->d_books, sizeof(int2) * (size_t)book_int2) &&
             alloc((void **)&c->d_log, sizeof(int32_t) * lob::kTradeFields * (size_t)log_rec) &&
             alloc((void **)&c->d_stage, c->stage_bytes) &&
+            alloc((void **)&c->d_exec_acts, sizeof(int32_t) * 4 * 8 * (size_t)c->n_books) &&
+            alloc((void **)&c->d_exec_aux, sizeof(int64_t) * 2 * (size_t)c->n_books) &&
             hipHostMalloc((void **)&c->h_stage, c->stage_bytes, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     g_create_error = "device allocation failed";
@@ -530,6 +534,49 @@ lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, cons
   a.fill_counts = F > 0 ? agent_fill_counts : nullptr;
   a.agent_tid = agent_tid;
   return run_process(ctx, a, (hipStream_t)stream);
+}
+
+lob_status lob_exec_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window,
+                         int32_t W, const int32_t *action_qty, const lob_exec_params *params,
+                         lob_exec_state *state, int32_t *obs, double *reward, int32_t *agent_fills, int32_t F,
+                         int32_t *agent_fill_counts, void *stream) {
+  lob_status st = check_list(ctx, n_books);
+  if (st != LOB_OK) return st;
+  if (W < 1 || W > 256) return fail(ctx, LOB_EINVAL, "W out of 1..256");
+  if (F < 1) return fail(ctx, LOB_EINVAL, "F < 1");
+  if (!params) return fail(ctx, LOB_EINVAL, "params is NULL");
+  if (n_books == 0) return LOB_OK;
+  if (!window || !aligned16(window)) return fail(ctx, LOB_EINVAL, "window NULL or not 16-byte aligned");
+  if (!action_qty || !state || !obs || !reward || !agent_fills || !agent_fill_counts)
+    return fail(ctx, LOB_EINVAL, "a buffer is NULL");
+  if ((reinterpret_cast<uintptr_t>(obs) & 3) || (reinterpret_cast<uintptr_t>(reward) & 7) ||
+      (reinterpret_cast<uintptr_t>(state) & 7))
+    return fail(ctx, LOB_EINVAL, "obs / reward / state misaligned");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = lob::launch_exec_prepare(ctx->d_hdr, ctx->d_books, book_ids, n_books, ctx->n_books, window, W,
+                                          action_qty, *params, state, ctx->d_exec_acts, ctx->d_exec_aux, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "exec prepare");
+  // the matcher: data then agent orders; level-1 row of every data message into the
+  // first 4W ints of the book's observation row; trades logged for the reward
+  lob::ProcArgs a = lob::base_args(ctx, book_ids, n_books);
+  a.msgs = window;
+  a.w1 = W;
+  a.msgs2 = ctx->d_exec_acts;
+  a.w2 = 4;
+  a.l2_mode = LOB_L2_PER_MESSAGE;
+  a.levels = 1;
+  a.l2_out = obs;
+  a.l2_stride = 6 * (int64_t)W + 8;
+  a.fills = agent_fills;
+  a.fill_cap = F;
+  a.fill_counts = agent_fill_counts;
+  a.agent_tid = params->agent_tid;
+  st = run_process(ctx, a, s);
+  if (st != LOB_OK) return st;
+  e = lob::launch_exec_finish(ctx->d_hdr, book_ids, n_books, ctx->n_books, ctx->d_log, window, W, *params, state, obs,
+                              reward, agent_fills, F, agent_fill_counts, ctx->d_exec_aux, s);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "exec finish");
 }
 
 lob_status lob_read_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *l2_out, void *stream) {

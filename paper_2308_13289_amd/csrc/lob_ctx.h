@@ -24,6 +24,13 @@ hipError_t launch_read_trades(BookHdr *hdr, const int32_t *log, const int32_t *i
                               int32_t *out, int64_t max_records, int64_t *counts, int64_t *offsets,
                               hipStream_t s);
 hipError_t launch_selftest(int32_t *out, hipStream_t s);
+hipError_t launch_exec_prepare(const BookHdr *hdr, const int2 *books, const int32_t *ids, int n, int n_total,
+                               const int32_t *window, int W, const int32_t *action_qty, const lob_exec_params &p,
+                               lob_exec_state *state, int32_t *acts, int64_t *aux, hipStream_t s);
+hipError_t launch_exec_finish(BookHdr *hdr, const int32_t *ids, int n, int n_total, const int32_t *log,
+                              const int32_t *window, int W, const lob_exec_params &p, lob_exec_state *state,
+                              int32_t *obs, double *reward, const int32_t *fills, int F, const int32_t *fill_counts,
+                              const int64_t *aux, hipStream_t s);
 hipError_t launch_seed_l2(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
                           const int32_t *l2, const int32_t *times, int tid, hipStream_t s);
 hipError_t launch_process_small(const ProcArgs &a, hipStream_t s);
@@ -54,6 +61,10 @@ struct lob_ctx {
   bool ragged_pending = false;
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // execution steps: the agent orders of each listed book [n_books][4][8] and where
+  // its trades of the step start in its log, with its trade count [n_books][2]
+  int32_t *d_exec_acts = nullptr;
+  int64_t *d_exec_aux = nullptr;
 };
 
 

@@ -58,6 +58,8 @@ struct ProcArgs {
   int32_t l2_mode;     // 0 none, 1 per message (indexed like source 1), 2 final (per listed book)
   int32_t levels;
   int32_t *l2_out;
+  int64_t l2_stride;   // l2_mode 1: 0 = rows by source-1 message index; else listed book i's
+                       // rows start at l2_out + i * l2_stride (int32 elements)
   // agent fills (step form)
   int32_t *fills;      // [n][fill_cap][6] or nullptr
   int32_t fill_cap;

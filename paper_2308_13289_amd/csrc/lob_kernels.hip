@@ -372,7 +372,7 @@ __device__ __forceinline__ void process_msg(const View<SPILL> &B, State &st, int
 // not decrease, so the scalar path per message only dispatches.
 template <bool SPILL>
 __device__ __forceinline__ void process_all(const View<SPILL> &B, State &st, const ProcArgs &a, long long beg1,
-                                            long long n1, long long beg2, long long n2, bool l2_each,
+                                            long long n1, long long beg2, long long n2, int32_t *l2_rows,
                                             int *scratch) {
   const int l = lane_id();
   const long long total = n1 + n2;
@@ -410,7 +410,7 @@ __device__ __forceinline__ void process_all(const View<SPILL> &B, State &st, con
       const int c = rdlane(code, j);
       process_msg(B, st, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
                   rdlane(v.w, j));
-      if (l2_each && k0 + j < n1) write_l2(B, st, a.levels, a.l2_out + (beg1 + k0 + j) * 4 * a.levels, scratch);
+      if (l2_rows && k0 + j < n1) write_l2(B, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels, scratch);
     }
   }
 }
@@ -477,7 +477,11 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int *scratch) {
     }
   }
   const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
-  process_all(B, st, a, beg1, n1, (long long)i * a.w2, n2, a.l2_mode == 1, scratch);
+  // per-message L2 rows of source 1: contiguous by message index, or l2_stride
+  // int32 apart per listed book
+  int32_t *l2_rows = a.l2_mode != 1 ? nullptr
+                     : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
+  process_all(B, st, a, beg1, n1, (long long)i * a.w2, n2, l2_rows, scratch);
   if (a.l2_mode == 2) write_l2(B, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels, scratch);
 
   // LDS window -> HBM

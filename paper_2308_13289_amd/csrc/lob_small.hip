@@ -480,7 +480,7 @@ __device__ __forceinline__ long long wave_sum(int v) {
 // The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
 // form's agent orders) msgs2[beg2, beg2 + n2), in 64-message chunks.
 __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, const ProcArgs &a, long long beg1,
-                                            long long n1, long long beg2, long long n2, bool l2_each) {
+                                            long long n1, long long beg2, long long n2, int32_t *l2_rows) {
   const int l = lane_id();
   const long long total = n1 + n2;
 #pragma nounroll
@@ -523,7 +523,7 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
       const int c = rdlane(code, j);
       process_msg(bk, st, sg, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
                   rdlane(v.w, j));
-      if (l2_each && k0 + j < n1) write_l2(bk, st, a.levels, a.l2_out + (beg1 + k0 + j) * 4 * a.levels);
+      if (l2_rows && k0 + j < n1) write_l2(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
     }
   }
 }
@@ -610,7 +610,11 @@ __device__ void run_book(const ProcArgs &a, int i) {
     }
   }
   const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
-  process_all(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, a.l2_mode == 1);
+  // per-message L2 rows of source 1: contiguous by message index, or l2_stride
+  // int32 apart per listed book
+  int32_t *l2_rows = a.l2_mode != 1 ? nullptr
+                     : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
+  process_all(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
   flush(st, sg);
   if (a.l2_mode == 2) write_l2(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 

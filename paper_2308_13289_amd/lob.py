@@ -25,6 +25,20 @@ STATUS_DTYPE = np.dtype([(n, np.int64) for n in (
 assert STATUS_DTYPE.itemsize == 96
 
 
+# execution environment (lob_exec_state / lob_exec_params in lob.h)
+EXEC_STATE_DTYPE = np.dtype([("task_side", np.int32), ("task_qty", np.int32), ("exec_qty", np.int32),
+                             ("done", np.int32), ("revenue", np.int64), ("p_init", np.int32),
+                             ("start_s", np.int32), ("start_ns", np.int32), ("end_s", np.int32),
+                             ("next_oid", np.int32), ("flags", np.int32)])
+assert EXEC_STATE_DTYPE.itemsize == 48
+EXEC_TRADES_MISSING = 1
+
+
+class ExecParams(ctypes.Structure):
+    _fields_ = [("tick", ctypes.c_int32), ("passive_ticks", ctypes.c_int32), ("agent_tid", ctypes.c_int32),
+                ("keep_trades", ctypes.c_int32), ("lam", ctypes.c_double)]
+
+
 class LobError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"liblob status {status}: {msg}")
@@ -51,7 +65,8 @@ class Plan(ctypes.Structure):
 _lib = None
 EXPORTS = ["lob_create", "lob_destroy", "lob_last_error", "lob_info", "lob_set_plan", "lob_get_plan",
            "lob_process_messages", "lob_process_ragged", "lob_autotune_ragged", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
-           "lob_read_book", "lob_write_book", "lob_reset", "lob_seed_l2", "lob_selftest", "lob_windows"]
+           "lob_read_book", "lob_write_book", "lob_reset", "lob_seed_l2", "lob_selftest", "lob_windows",
+           "lob_exec_step"]
 
 
 def load(path=None):
@@ -97,6 +112,8 @@ def load(path=None):
     L.lob_write_book.argtypes = [vp, vp, i32, vp, i32, vp]
     L.lob_reset.restype = i32
     L.lob_reset.argtypes = [vp, vp, i32, vp]
+    L.lob_exec_step.restype = i32
+    L.lob_exec_step.argtypes = [vp, vp, i32, vp, i32, vp, ctypes.POINTER(ExecParams), vp, vp, vp, vp, i32, vp, vp]
     L.lob_windows.restype = i32
     L.lob_windows.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, vp]
     L.lob_seed_l2.restype = i32
@@ -306,6 +323,19 @@ class Context:
     def reset(self, book_ids=None, stream=None):
         ids, n = self._ids(book_ids, None)
         self._check(self._lib.lob_reset(self._h, ids, n, _stream(stream, self.device)))
+
+    def exec_step(self, window, action_qty, state, obs, reward, fills, fill_counts, tick=100, passive_ticks=1,
+                  agent_tid=-1, keep_trades=False, lam=0.0, book_ids=None, stream=None):
+        """Execution-environment step (lob_exec_step): window[n][W][8], action_qty[n][4]
+        int32, state = uint8 device tensor of n * 48 bytes (EXEC_STATE_DTYPE), obs
+        [n][6W+8] int32, reward [n] float64, fills [n][F][6], fill_counts [n]."""
+        ids, n = self._ids(book_ids, window.shape[0])
+        p = ExecParams(int(tick), int(passive_ticks), int(agent_tid), int(bool(keep_trades)), float(lam))
+        self._check(self._lib.lob_exec_step(
+            self._h, ids, n, _ptr(window, torch.int32, "window"), int(window.shape[1]),
+            _ptr(action_qty, torch.int32, "action_qty"), ctypes.byref(p), _ptr(state, torch.uint8, "state"),
+            _ptr(obs, torch.int32, "obs"), _ptr(reward, torch.float64, "reward"), _ptr(fills, torch.int32, "fills"),
+            int(fills.shape[1]), _ptr(fill_counts, torch.int32, "fill_counts"), _stream(stream, self.device)))
 
     def seed_l2(self, l2, times=None, init_tid=0, book_ids=None, stream=None):
         """Start books from L2 snapshots l2[n][2][levels][2] (device int32); times[n][2]
