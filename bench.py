@@ -418,6 +418,47 @@ def bench_step(args, n_books=8192, n_steps=1000, window=100, fills_cap=32):
     return res
 
 
+def _time_plan(w, plan, reps, warmup=1):
+    """msgs/s of one plain process launch over workload w with the given plan (books
+    reset before every launch, final L2), plus a bit-exact spot check."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    lens = np.diff(w.offs)
+    ctx = lob.Context(w.caps, l2_levels=LEVELS, trade_log_records=w.caps.astype(np.int64) + 2 * lens)
+    ctx.set_plan(**plan)
+    d_msgs = torch.from_numpy(w.msgs).to(dev)
+    d_offs = torch.from_numpy(w.offs).to(dev)
+    l2 = torch.zeros((w.n_books, 2, LEVELS, 2), dtype=torch.int32, device=dev)
+    ms = []
+    for k in range(warmup + reps):
+        ctx.reset(stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.process(d_msgs, d_offs, l2_mode=lob.L2_FINAL, l2_out=l2, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if k >= warmup:
+            ms.append(a.elapsed_time(b))
+    ok, n = verify_sample(ctx, w, l2, n_check=8)
+    ctx.close()
+    m = float(np.median(ms))
+    return {"plan": plan, "kernel_ms": m, "msgs_per_s": w.n_msgs / (m / 1e3), "bit_exact_sample_books": n, "ok": ok}
+
+
+def bench_layout(args, reps=3):
+    """Sorted sides (this library's layout; registers or LDS) against the paper's
+    unsorted fixed-size arrays (a full search of the side per trade and per cancel),
+    on the headline workload and on deep books (capacity 1000, half full)."""
+    out = {}
+    w = W.c1(threads=host_cores())
+    out["c1_4096x10100_cap100"] = [_time_plan(w, p, reps) for p in
+                                   ({"registers": 1}, {"registers": 0}, {"layout": 1})]
+    del w
+    w = W.uniform(1024, 5000, cap=1000, tag=21, threads=host_cores(), name="deep1024x5000c1000")
+    out["deep_1024x6000_cap1000"] = [_time_plan(w, p, reps) for p in ({"registers": 0}, {"layout": 1})]
+    return out
+
+
 # the paper's own timings (RTX 2080 Ti, JAX; Tables 1-4), quoted as context
 PAPER_MS = {
     "single_book": {10: {"add": 0.115, "cancel": 0.081, "match": 0.184},
@@ -519,7 +560,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="all", choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro"])
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout"])
     ap.add_argument("--tune-trials", type=int, default=16)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
@@ -548,6 +590,9 @@ def main():
     if args.workload == "micro":
         print(json.dumps(bench_micro(args)), flush=True)
         return
+    if args.workload == "layout":
+        print(json.dumps(bench_layout(args)), flush=True)
+        return
     t0 = time.perf_counter()
     if args.workload in ("c1", "all"):
         w = W.c1(threads=host_cores())
@@ -570,6 +615,9 @@ def main():
         log(f"step form: {res['step_form']['steps_per_s']:.0f} steps/s, "
             f"p99 {res['step_form']['eager_step_ms']['p99']:.3f} ms")
         res["serving"] = bench_serving(args)
+        res["layout_ablation"] = bench_layout(args, reps=2)
+        log("layout ablation (C1 msgs/s): " + ", ".join(
+            f"{r['plan']}: {r['msgs_per_s'] / 1e9:.2f} G" for r in res["layout_ablation"]["c1_4096x10100_cap100"]))
         res["paper_tables"] = bench_micro(args, trials=200, trials_many=50)
         log("paper tables: single-book add/cancel/match at N=100: " + ", ".join(
             f"{res['paper_tables']['single_book'][100][op]['mean_ms'] * 1e3:.1f} us" for op in W.MICRO_OPS))

@@ -135,7 +135,12 @@ typedef struct {
                               keeps each whole book in registers while its
                               messages run (larger books use the LDS window);
                               0: always the LDS window                          */
-  int32_t reserved;
+  int32_t layout;          /* 0: each side kept sorted in priority order (the
+                              kernels above); 1: the paper's layout -- unsorted
+                              fixed-size arrays, first free position for an add,
+                              a search of the whole side per trade and per cancel
+                              -- with the whole book in LDS (for comparison; same
+                              results; capacity limited by LDS)                 */
 } lob_plan;
 
 typedef struct lob_ctx lob_ctx;

@@ -12,12 +12,12 @@ Plain and step by step, one book at a time:
   3. the observation (Section 5.2.2) and the reward of eqs. (rewardfunc) and (vwap),
      Section 5.2.4, are formed from those level-1 rows and the step's trades.
 
-Readings (the paper leaves these open): R10 the mid price is floor((ask + bid) / 2)
+Readings (the paper leaves these open): R15 the mid price is floor((ask + bid) / 2)
 in price units and a missing best price reads -1 (mid, passive and spread then read
--1 too, a missing side's quantity reads 0); R11 agent orders carry the time of the
-step's last data message and consecutive ids; R12 Q_j is capped so that the
+-1 too, a missing side's quantity reads 0); R16 agent orders carry the time of the
+step's last data message and consecutive ids; R17 Q_j is capped so that the
 executed quantity never exceeds the task size, and a step without trades has
-reward 0; R13 the drift uses the mid price after the step's last data message (0 if
+reward 0; R18 the drift uses the mid price after the step's last data message (0 if
 missing); the episode is over once the current time reaches end_s.
 """
 import numpy as np
@@ -49,7 +49,7 @@ class ExecEnv:
         return (int(a[0, 0]) if len(a) else -1), (int(b[0, 0]) if len(b) else -1)
 
     def _prices(self, ask, bid):
-        """far touch, mid, near touch, passive (Section 5.2.2 and 5.2.3; R10)"""
+        """far touch, mid, near touch, passive (Section 5.2.2 and 5.2.3; R15)"""
         buy = self.side == 1
         far = ask if buy else bid
         near = bid if buy else ask
@@ -66,7 +66,7 @@ class ExecEnv:
         window = np.asarray(window, np.int32)
         valid = [m for m in window if 1 <= m[0] <= 4]
         t = (int(valid[-1][6]), int(valid[-1][7])) if valid else self.last_time
-        # 1. the agent's orders (R11)
+        # 1. the agent's orders (R16)
         orders = []
         remaining = self.task_qty - self.exec_qty
         if not self.done and remaining > 0:
@@ -112,7 +112,7 @@ class ExecEnv:
             obs[4 * W + k] = ask - bid if ask >= 0 and bid >= 0 else -1
             obs[5 * W + k] = (int(aq) if aq > 0 else 0) - (int(bq) if bq > 0 else 0)
             mids.append(mid)
-        # reward (eqs. rewardfunc, vwap; R12)
+        # reward (eqs. rewardfunc, vwap; R17)
         fills = [tr for tr in trades if tr[6] == self.tid or tr[7] == self.tid]
         A = B = 0
         for tr in fills:

@@ -26,7 +26,7 @@
  *       Section 5.1.1 are never processed.  A side other than +1 / -1 is a no-op.
  *   R8  A limit or market message with Q <= 0 trades nothing and rests nothing,
  *       which is what add-then-clean-up gives (Table 2 uses Q_a = 0).
- *   R9  Book initialisation from an L2 snapshot (Section 5.1.1): one order per
+ *   R14 Book initialisation from an L2 snapshot (Section 5.1.1): one order per
  *       level with the level's summed quantity; the ids -9000, -9001, ... are
  *       handed out level by level, ask before bid, the column order of a LOBSTER
  *       order-book row.  The paper leaves trader id and time of these orders open:
@@ -315,7 +315,7 @@ int32_t orc_dump(const orc_book *b, int32_t side, int32_t *out) {
   return n;
 }
 
-/* Section 5.1.1: the book at the start of a window comes from its L2 snapshot (R9). */
+/* Section 5.1.1: the book at the start of a window comes from its L2 snapshot (R14). */
 int32_t orc_seed_l2(orc_book *b, const int32_t *l2, int32_t levels, int32_t tid, int32_t ts, int32_t tns) {
   for (int32_t i = 0; i < b->N; ++i) {
     set_empty(&b->A[i]);

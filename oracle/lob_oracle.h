@@ -97,7 +97,7 @@ int32_t orc_capacity(const orc_book *b);
  * entry (price, qty); entries with qty <= 0 are missing levels.  The book is
  * emptied and its counters cleared, then every present level becomes one order
  * holding the level's quantity, with trader id `tid` and time (ts, tns).  Order ids
- * start at -9000 and descend, level by level, ask before bid (R9).  A snapshot
+ * start at -9000 and descend, level by level, ask before bid (R14).  A snapshot
  * that is not a book -- prices not strictly ordered, bid >= ask, or more levels
  * than the capacity on a side -- leaves the book empty, sets ORC_FLAG_BAD_LOAD and
  * returns -1; otherwise returns the number of orders placed. */

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblob.so")
 SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_small.hip"),
-           os.path.join(CSRC, "lob_exec.hip"),
+           os.path.join(CSRC, "lob_exec.hip"), os.path.join(CSRC, "lob_unsorted.hip"),
            os.path.join(CSRC, "lob_api.cpp"), os.path.join(CSRC, "lob_serve.cpp"),
            os.path.join(CSRC, "lob_windows.cpp")]
 HEADERS = [os.path.join(CSRC, "lob_internal.h"), os.path.join(CSRC, "lob_ctx.h"),
@@ -35,8 +35,8 @@ def command(out):
             "-ffp-contract=off",
             "-Wall", "-Wno-unused-function",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-            SOURCES[0], SOURCES[1], SOURCES[2], "-x", "hip", SOURCES[3], SOURCES[4], "-x", "c++", SOURCES[5],
-            "-o", out]
+            SOURCES[0], SOURCES[1], SOURCES[2], SOURCES[3], "-x", "hip", SOURCES[4], SOURCES[5],
+            "-x", "c++", SOURCES[6], "-o", out]
 
 
 def up_to_date():

@@ -97,6 +97,16 @@ lob_status geometry(lob_ctx *c, int window, int cap_limit, int bpb_want, Geometr
 // the plan allows it and every such book fits in registers, else the LDS kernel.
 lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bpb, hipStream_t s) {
   if (a.n == 0) return LOB_OK;
+  if (c->plan.layout == 1) {  // the paper's unsorted arrays, whole book in LDS
+    const int per_wave = (lob::unsorted_lds_ints(cap_limit) + 1) / 2;
+    int b = std::max(1, std::min(16, bpb));
+    while (b > 1 && (size_t)b * per_wave * sizeof(int2) > c->max_lds) --b;
+    if ((size_t)per_wave * sizeof(int2) > c->max_lds) return fail(c, LOB_ECAP, "book does not fit in LDS");
+    a.bpb = b;
+    a.lds_int2_per_wave = per_wave;
+    hipError_t e = lob::launch_process_unsorted(a, s);
+    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+  }
   if (c->plan.registers && cap_limit <= lob::small_book_slots()) {
     a.bpb = std::max(1, std::min(16, bpb));
     hipError_t e = lob::launch_process_small(a, s);
@@ -219,6 +229,7 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_ragged_done, hipEventDisableTiming);
   if (e == hipSuccess) {  // advisory on this platform
     (void)lob::set_process_lds_limit(c->max_lds);
+    (void)lob::set_process_unsorted_lds_limit(c->max_lds);
   }
   if (e != hipSuccess) {
     g_create_error = std::string("context setup: ") + hipGetErrorString(e);
@@ -264,6 +275,9 @@ lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan) {
   if (plan->books_per_block_big < 1 || plan->books_per_block_big > 16)
     return fail(ctx, LOB_EINVAL, "books_per_block_big");
   if (plan->registers != 0 && plan->registers != 1) return fail(ctx, LOB_EINVAL, "registers");
+  if (plan->layout != 0 && plan->layout != 1) return fail(ctx, LOB_EINVAL, "layout");
+  if (plan->layout == 1 && (size_t)lob::unsorted_lds_ints(ctx->max_cap) * sizeof(int32_t) > ctx->max_lds)
+    return fail(ctx, LOB_ECAP, "layout 1: the largest book does not fit in LDS");
   for (int w : {plan->lds_slots, plan->lds_slots_big, plan->ragged_split > 0 ? plan->ragged_split : 1})
     if ((size_t)lds_int2_per_wave(std::min(w, ctx->max_cap), ctx->L) * sizeof(int2) >
         ctx->max_lds)

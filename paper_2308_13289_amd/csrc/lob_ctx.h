@@ -34,6 +34,9 @@ hipError_t launch_exec_finish(BookHdr *hdr, const int32_t *ids, int n, int n_tot
 hipError_t launch_seed_l2(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
                           const int32_t *l2, const int32_t *times, int tid, hipStream_t s);
 hipError_t launch_process_small(const ProcArgs &a, hipStream_t s);
+hipError_t launch_process_unsorted(const ProcArgs &a, hipStream_t s);
+hipError_t set_process_unsorted_lds_limit(size_t bytes);
+int unsorted_lds_ints(int cap);
 hipError_t launch_selftest_shift(int32_t *out, hipStream_t s);
 int small_book_slots();
 }  // namespace lob

@@ -56,7 +56,7 @@ class Plan(ctypes.Structure):
     _fields_ = [("lds_slots", ctypes.c_int32), ("books_per_block", ctypes.c_int32),
                 ("ragged_split", ctypes.c_int32), ("lds_slots_big", ctypes.c_int32),
                 ("ragged_order", ctypes.c_int32), ("books_per_block_big", ctypes.c_int32),
-                ("registers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("registers", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -222,7 +222,7 @@ class Context:
         p = self.get_plan()
         names = {f for f, _ in Plan._fields_}
         for k, v in kw.items():
-            if k not in names or k == "reserved":
+            if k not in names:
                 raise KeyError(f"lob_plan has no field {k!r}")
             setattr(p, k, int(v))
         self._check(self._lib.lob_set_plan(self._h, ctypes.byref(p)))

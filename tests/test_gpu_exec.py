@@ -24,7 +24,7 @@ from paper_2308_13289_amd import workload as W  # noqa: E402
 AGENT = -1
 
 
-@pytest.mark.parametrize("res", [{"registers": 1}, {"registers": 0}])
+@pytest.mark.parametrize("res", [{"registers": 1}, {"registers": 0}, {"layout": 1}])
 def test_exec_steps_match_oracle(res):
     n_books, cap, Wn, n_steps, F = 24, 100, 100, 16, 64
     w = W.uniform(n_books, Wn * n_steps, cap=cap, tag=13)

@@ -20,7 +20,7 @@ from paper_2308_13289_amd import workload as W  # noqa: E402
 
 CASES = [(N, op, None) for N in (10, 100, 1000) for op in W.MICRO_OPS] + \
         [(100, "market", q) for q in (0, 10, 500, 1000, 10000)]
-RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}}
+RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}, "unsorted": {"layout": 1}}
 
 
 def oracle_after(N, seeds, msg):

@@ -47,7 +47,7 @@ def test_selftest_primitives():
     np.testing.assert_array_equal(out[512:576], np.where(lanes == 17, -9, x))
 
 
-RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}}
+RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}, "unsorted": {"layout": 1}}
 
 
 @pytest.mark.parametrize("res", ["regs", "lds"])
@@ -121,7 +121,9 @@ def test_plans_agree_c0(plan):
     {"registers": 0},
     {"registers": 0, "lds_slots": 128},
     {"lds_slots": 200},
-], ids=["default", "spill128", "persistent", "split", "split_spill", "lds", "lds_spill128", "regs_tail200"])
+    {"layout": 1, "books_per_block": 2},
+], ids=["default", "spill128", "persistent", "split", "split_spill", "lds", "lds_spill128", "regs_tail200",
+        "unsorted"])
 def test_ragged_mixed_capacities(plan):
     """Capacities {50,100,500,1000} and uneven stream lengths in one call."""
     w = W.ragged(n_books=96, max_flow=4000)
@@ -197,7 +199,8 @@ def test_small_capacity_rejects_and_deep_books():
     msgs = np.array([m for s in streams for m in s], np.int32)
     offs = np.concatenate([[0], np.cumsum([len(s) for s in streams])]).astype(np.int64)
     caps = np.full(16, 300, np.int32)
-    for plan in ({}, {"lds_slots": 64}, {"lds_slots": 200}, {"registers": 0}, {"registers": 0, "lds_slots": 64}):
+    for plan in ({}, {"lds_slots": 64}, {"lds_slots": 200}, {"registers": 0}, {"registers": 0, "lds_slots": 64},
+                 {"layout": 1}):
         g = run_gpu(caps, msgs, offs, l2_mode=lob.L2_PER_MESSAGE, plan=plan)
         o = run_oracle(caps, msgs, offs, l2_mode=O.L2_PER_MESSAGE)
         assert_same(g, o, f"deep books {plan}")

@@ -1,4 +1,4 @@
-"""Execution-environment oracle (JAX-LOB Section 5.2; readings R10-R13 in
+"""Execution-environment oracle (JAX-LOB Section 5.2; readings R15-R18 in
 oracle/exec_env.py), pinned by hand-worked steps: the observation fields, the
 VWAP reward of eqs. (rewardfunc) and (vwap), the forced market order one minute
 before the end, and the cap of the executed quantity at the task size."""

@@ -1,5 +1,5 @@
 """Oracle book initialisation from an L2 snapshot (JAX-LOB Section 5.1.1; reading
-R9): pinned by a hand-worked example, by the snapshot round trip (seed, then L2,
+R14): pinned by a hand-worked example, by the snapshot round trip (seed, then L2,
 gives the snapshot back), by refusal of snapshots that are not books, and by the
 initial-order cancel rule acting on seeded orders."""
 import numpy as np
