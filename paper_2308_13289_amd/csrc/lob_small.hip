@@ -443,30 +443,42 @@ __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L,
 }
 
 // One message (Section 4.2) given its case code: 1/2 limit sell/buy, 3/4 market
-// sell/buy, 5/6 cancel-or-delete on the ask/bid side, 0 not processed.
+// sell/buy, 5/6 cancel-or-delete on the ask/bid side, 0 not processed.  Limit:
+// match, then rest the remainder as one new order (item 1); market: match at
+// price 0 (sell) / max_int (buy), drop the rest (item 3); cancel and delete are
+// the same operation (item 2).  One straight call sequence per case, so that no
+// flag derived from the case has to survive across branches.
 __device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, int P, int Q, int oid, int tid,
                                             int ts, int tns) {
-  if (code == 0) return;
-  const bool buys = (code & 1) == 0;
-  if (code <= 4) {
-    // limit: match, then rest the remainder as one new order (item 1); market: match
-    // at price 0 (sell) / max_int (buy) and drop the rest (item 3)
-    const bool limit = code <= 2;
-    const int lim = limit ? P : (buys ? INT_MAX : 0);
-    const int rem = buys ? match<0>(bk, st, sg, lim, Q, oid, tid, ts, tns)
-                         : match<1>(bk, st, sg, lim, Q, oid, tid, ts, tns);
-    if (rem > 0) {
-      if (!limit)
-        st.market_discarded += rem;
-      else if (buys)
-        insert<1>(bk, st, P, rem, oid, tid, ts, tns);
-      else
-        insert<0>(bk, st, P, rem, oid, tid, ts, tns);
+  switch (code) {
+    case 1: {
+      const int rem = match<1>(bk, st, sg, P, Q, oid, tid, ts, tns);
+      if (rem > 0) insert<0>(bk, st, P, rem, oid, tid, ts, tns);
+      break;
     }
-  } else if (buys) {
-    cancel<1>(bk, st, oid, Q, P);
-  } else {
-    cancel<0>(bk, st, oid, Q, P);
+    case 2: {
+      const int rem = match<0>(bk, st, sg, P, Q, oid, tid, ts, tns);
+      if (rem > 0) insert<1>(bk, st, P, rem, oid, tid, ts, tns);
+      break;
+    }
+    case 3: {
+      const int rem = match<1>(bk, st, sg, 0, Q, oid, tid, ts, tns);
+      if (rem > 0) st.market_discarded += rem;
+      break;
+    }
+    case 4: {
+      const int rem = match<0>(bk, st, sg, INT_MAX, Q, oid, tid, ts, tns);
+      if (rem > 0) st.market_discarded += rem;
+      break;
+    }
+    case 5:
+      cancel<0>(bk, st, oid, Q, P);
+      break;
+    case 6:
+      cancel<1>(bk, st, oid, Q, P);
+      break;
+    default:
+      break;
   }
 }
 
@@ -518,12 +530,14 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
       st.market_qty += wave_sum(((code == 3) | (code == 4)) ? qpos : 0);
     }
     st.n_msgs += cnt;
+    // messages of this chunk that come from source 1 (they get per-message L2 rows)
+    const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
 #pragma nounroll
     for (int j = 0; j < cnt; ++j) {
       const int c = rdlane(code, j);
       process_msg(bk, st, sg, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
                   rdlane(v.w, j));
-      if (l2_rows && k0 + j < n1) write_l2(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+      if (l2_rows && j < c1) write_l2(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
     }
   }
 }
