@@ -1,7 +1,9 @@
 """Compile liblob.so (the HIP library behind include/lob.h) for gfx950, in-tree."""
 import os
+import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -35,8 +37,10 @@ def command(out):
             "-ffp-contract=off",
             "-Wall", "-Wno-unused-function",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-            SOURCES[0], SOURCES[1], SOURCES[2], SOURCES[3], "-x", "hip", SOURCES[4], SOURCES[5],
-            "-x", "c++", SOURCES[6], "-o", out]
+            # the host-only sources go in as HIP too: a "-x c++" input makes hipcc
+            # drop --offload-arch for the whole command
+            SOURCES[0], SOURCES[1], SOURCES[2], SOURCES[3], "-x", "hip", SOURCES[4], SOURCES[5], SOURCES[6],
+            "-o", out]
 
 
 def up_to_date():
@@ -44,6 +48,18 @@ def up_to_date():
         return False
     t = os.path.getmtime(LIB)
     return all(os.path.getmtime(p) <= t for p in SOURCES + HEADERS)
+
+
+def code_object_archs(lib):
+    """Target names of the device code objects embedded in a built library."""
+    objdump = "/opt/rocm/llvm/bin/llvm-objdump"
+    if not os.path.exists(objdump):
+        return None
+    with tempfile.TemporaryDirectory() as d:
+        copy = os.path.join(d, "lib.so")
+        shutil.copy(lib, copy)
+        subprocess.run([objdump, "--offloading", copy], cwd=d, capture_output=True, text=True)
+        return sorted({f.rsplit("--", 1)[-1] for f in os.listdir(d) if "hipv4-amdgcn" in f})
 
 
 def build(force=True, verbose=False):
@@ -58,6 +74,10 @@ def build(force=True, verbose=False):
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building liblob.so")
+    archs = code_object_archs(tmp)
+    if archs is not None and archs != [ARCH]:
+        os.remove(tmp)
+        raise RuntimeError(f"liblob.so built for {archs}, expected [{ARCH!r}]")
     os.replace(tmp, LIB)
     return LIB
 
