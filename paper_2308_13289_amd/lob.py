@@ -184,7 +184,12 @@ class Context:
         cfg.device = device
         self._logs = None
         if trade_log_records is not None:
-            self._logs = np.ascontiguousarray(trade_log_records, dtype=np.int64)
+            logs = np.asarray(trade_log_records, dtype=np.int64)
+            if logs.ndim == 0:
+                logs = np.full(caps.shape[0], int(logs), np.int64)
+            if logs.shape != caps.shape:
+                raise ValueError("trade_log_records: one entry per book (or one for all)")
+            self._logs = np.ascontiguousarray(logs)
             cfg.trade_log_records_host = self._logs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         cfg.trade_log_default = int(trade_log_default)
         cfg.flags = 0
