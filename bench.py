@@ -455,7 +455,8 @@ def bench_layout(args, reps=3):
                                    ({"registers": 1}, {"registers": 0}, {"layout": 1})]
     del w
     w = W.uniform(1024, 5000, cap=1000, tag=21, threads=host_cores(), name="deep1024x5000c1000")
-    out["deep_1024x6000_cap1000"] = [_time_plan(w, p, reps) for p in ({"registers": 0}, {"layout": 1})]
+    out["deep_1024x6000_cap1000"] = [_time_plan(w, p, reps) for p in
+                                     ({"registers": 1}, {"registers": 0}, {"layout": 1})]
     return out
 
 

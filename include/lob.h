@@ -131,10 +131,11 @@ typedef struct {
                               (longest-processing-time list scheduling), 0 = as
                               listed                                            */
   int32_t books_per_block_big; /* books per workgroup of the second ragged launch */
-  int32_t registers;       /* 1: a launch whose books all have capacity <= 128
-                              keeps each whole book in registers while its
-                              messages run (larger books use the LDS window);
-                              0: always the LDS window                          */
+  int32_t registers;       /* 1: while its messages run, each book keeps the first
+                              128 orders of a side in registers -- the whole book
+                              when the launch's capacities are <= 128, else with
+                              the rest in LDS when that fits (larger books use the
+                              LDS window); 0: always the LDS window             */
   int32_t layout;          /* 0: each side kept sorted in priority order (the
                               kernels above); 1: the paper's layout -- unsorted
                               fixed-size arrays, first free position for an add,

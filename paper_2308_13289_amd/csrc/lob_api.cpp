@@ -107,10 +107,24 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
     hipError_t e = lob::launch_process_unsorted(a, s);
     return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
   }
-  if (c->plan.registers && cap_limit <= lob::small_book_slots()) {
-    a.bpb = std::max(1, std::min(16, bpb));
-    hipError_t e = lob::launch_process_small(a, s);
-    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+  if (c->plan.registers) {
+    if (cap_limit <= lob::small_book_slots()) {  // whole books in registers
+      a.bpb = std::max(1, std::min(16, bpb));
+      hipError_t e = lob::launch_process_small(a, false, s);
+      return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+    }
+    // the first 128 orders per side in registers, the rest in an LDS tail
+    const int tw = cap_limit - lob::small_book_slots();
+    const int per_wave = 6 * tw;
+    if ((size_t)per_wave * sizeof(int2) <= c->max_lds) {
+      int b = std::max(1, std::min(16, bpb));
+      while (b > 1 && (size_t)b * per_wave * sizeof(int2) > c->max_lds) --b;
+      a.W = tw;
+      a.bpb = b;
+      a.lds_int2_per_wave = per_wave;
+      hipError_t e = lob::launch_process_small(a, true, s);
+      return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+    }
   }
   Geometry g;
   lob_status st = geometry(c, window, cap_limit, bpb, &g);
@@ -230,6 +244,7 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
   if (e == hipSuccess) {  // advisory on this platform
     (void)lob::set_process_lds_limit(c->max_lds);
     (void)lob::set_process_unsorted_lds_limit(c->max_lds);
+    (void)lob::set_process_small_lds_limit(c->max_lds);
   }
   if (e != hipSuccess) {
     g_create_error = std::string("context setup: ") + hipGetErrorString(e);

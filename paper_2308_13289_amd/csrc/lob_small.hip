@@ -48,8 +48,16 @@ struct Side {
   Chunk c0, c1;
 };
 
+// TAIL form: the orders of a side past its first 128 live in LDS, worst first --
+// entry t of a side holding n orders is slot n - 1 - t -- so orders enter and leave
+// the register window at the tail's end, the only place top-of-book traffic touches.
+struct Tail {
+  int2 *pq, *ot, *tt;
+};
+
 struct Book {
   Side ask, bid;  // side 0 = asks, side 1 = bids
+  Tail tl[2];     // TAIL form only
 };
 
 template <int SD>
@@ -58,6 +66,33 @@ __device__ __forceinline__ Side &side(Book &b) {
     return b.ask;
   else
     return b.bid;
+}
+
+__device__ __forceinline__ Chunk tail_get(const Tail &t, int i) {
+  const int2 a = t.pq[i], b = t.ot[i], c = t.tt[i];
+  Chunk v;
+  v.p = a.x;
+  v.q = a.y;
+  v.o = b.x;
+  v.t = b.y;
+  v.ts = c.x;
+  v.tns = c.y;
+  return v;
+}
+
+__device__ __forceinline__ void tail_put(const Tail &t, int i, const Chunk &v) {
+  t.pq[i] = make_int2(v.p, v.q);
+  t.ot[i] = make_int2(v.o, v.t);
+  t.tt[i] = make_int2(v.ts, v.tns);
+}
+
+__device__ __forceinline__ void pick(Chunk &x, bool c, const Chunk &v) {
+  x.p = c ? v.p : x.p;
+  x.q = c ? v.q : x.q;
+  x.o = c ? v.o : x.o;
+  x.t = c ? v.t : x.t;
+  x.ts = c ? v.ts : x.ts;
+  x.tns = c ? v.tns : x.tns;
 }
 
 // Pending trade records, one per lane; k of them (uniform) are pending.
@@ -203,8 +238,10 @@ __device__ __forceinline__ void put(Chunk &x, const Chunk &v, int lane) {
   x.tns = wl(x.tns, v.tns, lane);
 }
 
-// Slots (k, n) of a side move down by one (slot k is dropped).
-__device__ __forceinline__ void remove_at(Side &S, int k, int n) {
+// Slots (k, n) of a side move down by one (slot k < 128 is dropped); in the TAIL
+// form the tail's last entry (slot 128) moves up into slot 127.
+template <bool TAIL>
+__device__ __forceinline__ void remove_at(Side &S, const Tail &tl, int k, int n) {
   const int l = lane_id();
   if (n > kWave) {
     const Chunk in = edge(S.c1, 0);  // slot 64 moves to slot 63
@@ -213,18 +250,41 @@ __device__ __forceinline__ void remove_at(Side &S, int k, int n) {
       shift_dn(S.c0, l >= k);
       put(S.c0, in, 63);
     }
+    if constexpr (TAIL) {
+      if (n > kSlots) pick(S.c1, l == 63, tail_get(tl, n - kSlots - 1));
+    }
   } else {
     shift_dn(S.c0, l >= k);
   }
 }
 
-// The first m slots of a side (m >= 1) are removed: slot s takes slot s + m.
-__device__ __forceinline__ void remove_front(Side &S, int m, int n) {
+__device__ __forceinline__ void shift_front(Side &S, int m, int n);
+
+// The first m slots of a side (1 <= m <= 128) are removed: slot s takes slot s + m;
+// in the TAIL form the register positions freed at the end take the tail's last
+// entries.
+template <bool TAIL>
+__device__ __forceinline__ void remove_front(Side &S, const Tail &tl, int m, int n) {
   if (m == 1) {
-    remove_at(S, 0, n);
+    remove_at<TAIL>(S, tl, 0, n);
     return;
   }
-  if (m >= n) return;  // the side is empty now
+  const int l = lane_id();
+  const int nr = n < kSlots ? n : kSlots;
+  if (m < nr) shift_front(S, m, nr);
+  if constexpr (TAIL) {
+    if (n > kSlots) {
+      const int T = n - kSlots, k = m < T ? m : T, base = kSlots - m;
+      const int j0 = l - base, j1 = kWave + l - base;  // tail index T-1-j lands in position base + j
+      const bool t0 = (j0 >= 0) & (j0 < k), t1 = (j1 >= 0) & (j1 < k);
+      pick(S.c0, t0, tail_get(tl, t0 ? T - 1 - j0 : T - 1));
+      pick(S.c1, t1, tail_get(tl, t1 ? T - 1 - j1 : T - 1));
+    }
+  }
+}
+
+// Register slots [m, nr) move to [0, nr - m) (2 <= m < nr <= 128).
+__device__ __forceinline__ void shift_front(Side &S, int m, int n) {
   const int l = lane_id();
   const int src = (l + m) & 63;
   if (n <= kWave) {
@@ -265,11 +325,12 @@ __device__ __forceinline__ void remove_front(Side &S, int m, int n) {
 
 // Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
 // with limit price lim and quantity q.  Returns the unfilled quantity.
-template <int OPP>
+template <int OPP, bool TAIL>
 __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, int q, int a_oid, int a_tid, int ts,
                                      int tns) {
   Side &S = side<OPP>(bk);
-  const int n = st.n[OPP];
+  const Tail &tl = bk.tl[OPP];
+  int n = st.n[OPP];
   constexpr bool buyer = (OPP == 0);
   if (q <= 0 || n == 0) return q;
   const int bp = rdlane(S.c0.p, 0);
@@ -285,52 +346,60 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
     if (q < bq) {
       S.c0.q = wl(S.c0.q, bq - q, 0);
     } else {
-      remove_at(S, 0, n);
+      remove_at<TAIL>(S, tl, 0, n);
       st.n[OPP] = n - 1;
     }
     return 0;
   }
-  // the aggressor outlasts the best order: one prefix scan per chunk of crossing orders
+  // the aggressor outlasts the best order: one prefix scan per chunk of crossing
+  // orders; in the TAIL form a register window consumed whole is refilled from the
+  // tail and the scan goes on
   const int l = lane_id();
-  int removed = 0;
+  for (;;) {
+    const int nr = n < kSlots ? n : kSlots;
+    int removed = 0;
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    if (c == 1 && (removed < kWave || n <= kWave || q == 0)) break;
-    Chunk &F = c == 0 ? S.c0 : S.c1;
-    const bool valid = c * kWave + l < n;
-    const bool cross = valid & (buyer ? F.p <= lim : F.p >= lim);
-    const int qv = cross ? F.q : 0;
-    const int incl = scan_incl(qv);
-    const int excl = incl - qv;
-    const bool takes = cross & (excl < q);
-    const uint64_t mt = ballot(takes);
-    if (mt == 0) break;
-    const int ntr = popc(mt);
-    const bool full = cross & (incl <= q);
-    const int nfull = popc(ballot(full));
-    const int fill = takes ? min(qv, q - excl) : 0;
-    stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
-    fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
-    F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
-    const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
-    st.traded_qty += consumed;
-    st.n_trades += ntr;
-    q -= consumed;
-    removed += nfull;
-    if (nfull < kWave) break;
-  }
-  if (removed > 0) {
-    remove_front(S, removed, n);
-    st.n[OPP] = n - removed;
+    for (int c = 0; c < 2; ++c) {
+      if (c == 1 && (removed < kWave || nr <= kWave || q == 0)) break;
+      Chunk &F = c == 0 ? S.c0 : S.c1;
+      const bool valid = c * kWave + l < nr;
+      const bool cross = valid & (buyer ? F.p <= lim : F.p >= lim);
+      const int qv = cross ? F.q : 0;
+      const int incl = scan_incl(qv);
+      const int excl = incl - qv;
+      const bool takes = cross & (excl < q);
+      const uint64_t mt = ballot(takes);
+      if (mt == 0) break;
+      const int ntr = popc(mt);
+      const bool full = cross & (incl <= q);
+      const int nfull = popc(ballot(full));
+      const int fill = takes ? min(qv, q - excl) : 0;
+      stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
+      fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
+      F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
+      const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
+      st.traded_qty += consumed;
+      st.n_trades += ntr;
+      q -= consumed;
+      removed += nfull;
+      if (nfull < kWave) break;
+    }
+    if (removed > 0) {
+      remove_front<TAIL>(S, tl, removed, n);
+      n -= removed;
+      st.n[OPP] = n;
+    }
+    if (!TAIL || removed < kSlots || q == 0 || n == 0) break;
   }
   return q;
 }
 
 // Add (Section 4.1, item 1) on side SD: the new order goes behind every order with
 // an equal or better price, i.e. at its price-time position.
-template <int SD>
+template <int SD, bool TAIL>
 __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oid, int tid, int ts, int tns) {
   Side &S = side<SD>(bk);
+  const Tail &tl = bk.tl[SD];
   const int l = lane_id();
   const int n = st.n[SD];
   if (n >= st.cap) {
@@ -338,8 +407,9 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
     st.flags |= kFlagSideFull;
     return;
   }
-  int pos = popc(ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P) & lanes_below(n));
-  if (pos == kWave && n > kWave) pos += popc(ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P) & lanes_below(n - kWave));
+  const int nr = n < kSlots ? n : kSlots;
+  int pos = popc(ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P) & lanes_below(nr));
+  if (pos == kWave && nr > kWave) pos += popc(ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P) & lanes_below(nr - kWave));
   Chunk v;
   v.p = P;
   v.q = Q;
@@ -347,7 +417,40 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
   v.t = tid;
   v.ts = ts;
   v.tns = tns;
-  if (n >= kWave) {  // chunk 1 changes: slot 63 moves into slot 64, or the new order lands there
+  if constexpr (TAIL) {
+    if (pos == kSlots) {
+      // behind every register order: into the tail.  The tail orders ahead of it
+      // (equal or better price) are the entries [T - c, T); they move up by one and
+      // the new order takes entry T - c.
+      const int T = n - kSlots;
+      int c = 0;
+      for (int base = 0; base < T; base += kWave) {
+        const int t = base + l;
+        bool ahead = false;
+        if (t < T) {
+          const int p = tl.pq[t].x;
+          ahead = SD == 1 ? p >= P : p <= P;
+        }
+        c += popc(ballot(ahead));
+      }
+      for (int base = (T - 1) & ~63; base >= 0 && base + kWave > T - c; base -= kWave) {
+        const int t = base + l;
+        const bool mv = (t >= T - c) & (t < T);
+        Chunk e;
+        if (mv) e = tail_get(tl, t);
+        if (mv) tail_put(tl, t + 1, e);
+      }
+      if (l == 0) tail_put(tl, T - c, v);
+      st.n[SD] = n + 1;
+      return;
+    }
+    // the register window is full: its last order moves to the tail's end
+    if (n >= kSlots) {
+      const Chunk last = edge(S.c1, 63);
+      if (l == 0) tail_put(tl, n - kSlots, last);
+    }
+  }
+  if (nr >= kWave) {  // chunk 1 changes: slot 63 moves into slot 64, or the new order lands there
     const Chunk in = edge(S.c0, 63);
     shift_up(S.c1, l + kWave > pos);
     if (pos < kWave) put(S.c1, in, 0);
@@ -361,33 +464,78 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
   st.n[SD] = n + 1;
 }
 
+// The best-priority tail entry with pred (the highest entry index), -1 if none.
+template <typename Pred>
+__device__ __forceinline__ int tail_find(int T, Pred pred) {
+  const int l = lane_id();
+  for (int base = (T - 1) & ~63; base >= 0; base -= kWave) {
+    const int t = base + l;
+    const uint64_t m = ballot((t < T) && pred(t));
+    if (m) return base + 63 - __builtin_clzll(m);
+  }
+  return -1;
+}
+
 // Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders) on side SD.
-template <int SD>
+template <int SD, bool TAIL>
 __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, int price) {
   if (qty <= 0) return;
   Side &S = side<SD>(bk);
+  const Tail &tl = bk.tl[SD];
   const int l = lane_id();
   const int n = st.n[SD];
+  const int nr = n < kSlots ? n : kSlots;
   int k = -1;
-  uint64_t m = ballot(S.c0.o == oid) & lanes_below(n);
+  uint64_t m = ballot(S.c0.o == oid) & lanes_below(nr);
   if (m) {
     k = first_set(m);
-  } else if (n > kWave) {
-    m = ballot(S.c1.o == oid) & lanes_below(n - kWave);
+  } else if (nr > kWave) {
+    m = ballot(S.c1.o == oid) & lanes_below(nr - kWave);
     if (m) k = kWave + first_set(m);
   }
-  if (k < 0) {
-    m = ballot((S.c0.o <= -9000) & (S.c0.p == price)) & lanes_below(n);
+  int t = -1;  // TAIL: entry in the tail
+  if constexpr (TAIL) {
+    if (k < 0 && n > kSlots) t = tail_find(n - kSlots, [&](int e) { return tl.ot[e].x == oid; });
+  }
+  if (k < 0 && t < 0) {
+    m = ballot((S.c0.o <= -9000) & (S.c0.p == price)) & lanes_below(nr);
     if (m) {
       k = first_set(m);
-    } else if (n > kWave) {
-      m = ballot((S.c1.o <= -9000) & (S.c1.p == price)) & lanes_below(n - kWave);
+    } else if (nr > kWave) {
+      m = ballot((S.c1.o <= -9000) & (S.c1.p == price)) & lanes_below(nr - kWave);
       if (m) k = kWave + first_set(m);
     }
+    if constexpr (TAIL) {
+      if (k < 0 && n > kSlots)
+        t = tail_find(n - kSlots, [&](int e) { return tl.ot[e].x <= -9000 && tl.pq[e].x == price; });
+    }
   }
-  if (k < 0) {
+  if (k < 0 && t < 0) {
     st.cancel_miss++;
     return;
+  }
+  if constexpr (TAIL) {
+    if (t >= 0) {
+      const int T = n - kSlots;
+      const int2 pq = tl.pq[t];
+      const int P = uni(pq.x), Q = uni(pq.y);
+      st.cancelled_qty += min(qty, Q);
+      const int left = Q - qty;
+      if (left > 0) {
+        if (l == 0) tl.pq[t] = make_int2(P, left);
+      } else {
+        // the entries above it (better priority) move down by one
+        for (int base = (t + 1) & ~63; base < T; base += kWave) {
+          const int e = base + l;
+          const bool mv = (e > t) & (e < T);
+          Chunk x;
+          if (mv) x = tail_get(tl, e);
+          if (mv) tail_put(tl, e - 1, x);
+        }
+        st.n[SD] = n - 1;
+      }
+      return;
+    }
   }
   const bool lo = k < kWave;
   const int kl = k & 63;
@@ -400,7 +548,7 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
     else
       S.c1.q = wl(S.c1.q, left, kl);
   } else {
-    remove_at(S, k, n);
+    remove_at<TAIL>(S, tl, k, n);
     st.n[SD] = n - 1;
   }
 }
@@ -408,26 +556,43 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
 // L2 of one side: the first L distinct prices with their summed quantities into
 // out[0..L) as (price, qty); missing levels (-1, 0).  A level is a run of equal
 // prices in priority order; its quantity is the running sum at its last order minus
-// the running sum at the previous level's last order.
-__device__ __forceinline__ void l2_side(const Side &S, int n, int L, int2 *out) {
+// the running sum at the previous level's last order.  The slots are taken 64 at a
+// time in priority order: the two register chunks, then (TAIL form) the tail.
+template <bool TAIL>
+__device__ __forceinline__ void l2_side(const Side &S, const Tail &tl, int n, int L, int2 *out) {
   const int l = lane_id();
+  const int nr = n < kSlots ? n : kSlots;
   int levels = 0, q_before = 0, end_before = 0;
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
+  const int nchunks = TAIL ? (n + kWave - 1) / kWave : 2;
+  for (int c = 0; c < nchunks && levels < L; ++c) {
     if (c * kWave >= n) break;
-    const Chunk &F = c == 0 ? S.c0 : S.c1;
     const int s = c * kWave + l;
     const bool valid = s < n;
-    const int next_in = (c == 0 && n > kWave) ? rdlane(S.c1.p, 0) : 0;
-    const int next = shl1(F.p, next_in);
-    const bool is_last = valid & ((s + 1 == n) | (next != F.p));
-    const int incl = q_before + scan_incl(valid ? F.q : 0);
+    int p, q, next;
+    if (c < 2) {
+      const Chunk &F = c == 0 ? S.c0 : S.c1;
+      p = F.p;
+      q = F.q;
+      int next_in = 0;  // the price of slot 64(c+1)
+      if (c == 0 && nr > kWave) next_in = rdlane(S.c1.p, 0);
+      if constexpr (TAIL) {
+        if (c == 1 && n > kSlots) next_in = uni(tl.pq[n - kSlots - 1].x);
+      }
+      next = shl1(p, next_in);
+    } else {
+      // slot s is tail entry n - 1 - s
+      p = valid ? tl.pq[n - 1 - s].x : 0;
+      q = valid ? tl.pq[n - 1 - s].y : 0;
+      next = (s + 1 < n) ? tl.pq[n - 2 - s].x : 0;
+    }
+    const bool is_last = valid & ((s + 1 == n) | (next != p));
+    const int incl = q_before + scan_incl(valid ? q : 0);
     const uint64_t ml = ballot(is_last);
     const uint64_t below = ml & mask_lt();
     const int src = below ? 63 - __builtin_clzll(below) : 0;
     const int prev_end = from_lane(incl, src);
     const int lev = levels + popc(below);
-    if (is_last && lev < L) out[lev] = make_int2(F.p, incl - (below ? prev_end : end_before));
+    if (is_last && lev < L) out[lev] = make_int2(p, incl - (below ? prev_end : end_before));
     if (ml) end_before = rdlane(incl, 63 - __builtin_clzll(ml));
     levels += popc(ml);
     q_before = rdlane(incl, 63);
@@ -436,10 +601,11 @@ __device__ __forceinline__ void l2_side(const Side &S, int n, int L, int2 *out) 
   if (l >= have && l < L) out[l] = make_int2(-1, 0);
 }
 
+template <bool TAIL>
 __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L, int32_t *row) {
   int2 *o = reinterpret_cast<int2 *>(row);
-  l2_side(bk.ask, st.n[0], L, o);
-  l2_side(bk.bid, st.n[1], L, o + L);
+  l2_side<TAIL>(bk.ask, bk.tl[0], st.n[0], L, o);
+  l2_side<TAIL>(bk.bid, bk.tl[1], st.n[1], L, o + L);
 }
 
 // One message (Section 4.2) given its case code: 1/2 limit sell/buy, 3/4 market
@@ -448,34 +614,35 @@ __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L,
 // price 0 (sell) / max_int (buy), drop the rest (item 3); cancel and delete are
 // the same operation (item 2).  One straight call sequence per case, so that no
 // flag derived from the case has to survive across branches.
+template <bool TAIL>
 __device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, int P, int Q, int oid, int tid,
                                             int ts, int tns) {
   switch (code) {
     case 1: {
-      const int rem = match<1>(bk, st, sg, P, Q, oid, tid, ts, tns);
-      if (rem > 0) insert<0>(bk, st, P, rem, oid, tid, ts, tns);
+      const int rem = match<1, TAIL>(bk, st, sg, P, Q, oid, tid, ts, tns);
+      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
       break;
     }
     case 2: {
-      const int rem = match<0>(bk, st, sg, P, Q, oid, tid, ts, tns);
-      if (rem > 0) insert<1>(bk, st, P, rem, oid, tid, ts, tns);
+      const int rem = match<0, TAIL>(bk, st, sg, P, Q, oid, tid, ts, tns);
+      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
       break;
     }
     case 3: {
-      const int rem = match<1>(bk, st, sg, 0, Q, oid, tid, ts, tns);
+      const int rem = match<1, TAIL>(bk, st, sg, 0, Q, oid, tid, ts, tns);
       if (rem > 0) st.market_discarded += rem;
       break;
     }
     case 4: {
-      const int rem = match<0>(bk, st, sg, INT_MAX, Q, oid, tid, ts, tns);
+      const int rem = match<0, TAIL>(bk, st, sg, INT_MAX, Q, oid, tid, ts, tns);
       if (rem > 0) st.market_discarded += rem;
       break;
     }
     case 5:
-      cancel<0>(bk, st, oid, Q, P);
+      cancel<0, TAIL>(bk, st, oid, Q, P);
       break;
     case 6:
-      cancel<1>(bk, st, oid, Q, P);
+      cancel<1, TAIL>(bk, st, oid, Q, P);
       break;
     default:
       break;
@@ -491,6 +658,7 @@ __device__ __forceinline__ long long wave_sum(int v) {
 
 // The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
 // form's agent orders) msgs2[beg2, beg2 + n2), in 64-message chunks.
+template <bool TAIL>
 __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, const ProcArgs &a, long long beg1,
                                             long long n1, long long beg2, long long n2, int32_t *l2_rows) {
   const int l = lane_id();
@@ -535,9 +703,9 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
 #pragma nounroll
     for (int j = 0; j < cnt; ++j) {
       const int c = rdlane(code, j);
-      process_msg(bk, st, sg, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
+      process_msg<TAIL>(bk, st, sg, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
                   rdlane(v.w, j));
-      if (l2_rows && j < c1) write_l2(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+      if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
     }
   }
 }
@@ -564,7 +732,9 @@ __device__ __forceinline__ void store_chunk(const Chunk &x, int2 *base, int cap,
   }
 }
 
-__device__ void run_book(const ProcArgs &a, int i) {
+// TAIL form: tails of the two sides in LDS at `lds`, a.W entries each.
+template <bool TAIL>
+__device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   const int l = lane_id();
   const int book = a.book_ids ? uni(a.book_ids[i]) : i;
   if (book < 0 || book >= a.n_total) return;
@@ -573,7 +743,7 @@ __device__ void run_book(const ProcArgs &a, int i) {
   st.n[0] = uni(h->n[0]);
   st.n[1] = uni(h->n[1]);
   st.cap = uni(h->cap);
-  if (st.cap > kSlots) {  // not launched for such books; leave the book untouched
+  if (st.cap > (TAIL ? kSlots + a.W : kSlots)) {  // not launched for such books; leave the book untouched
     if (l == 0) h->flags |= kFlagBadLoad;
     return;
   }
@@ -606,6 +776,23 @@ __device__ void run_book(const ProcArgs &a, int i) {
   load_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0]);
   load_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1]);
   load_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1]);
+  if constexpr (TAIL) {
+    // slot s >= 128 of a side holding n orders is tail entry n - 1 - s
+    for (int sd = 0; sd < 2; ++sd) {
+      Tail &t = bk.tl[sd];
+      t.pq = lds + (sd * 3 + 0) * a.W;
+      t.ot = lds + (sd * 3 + 1) * a.W;
+      t.tt = lds + (sd * 3 + 2) * a.W;
+      const int n = st.n[sd];
+      const int2 *src = hb + (int64_t)sd * 3 * cap;
+      for (int s = kSlots + l; s < n; s += kWave) {
+        const int e = n - 1 - s;
+        t.pq[e] = src[s];
+        t.ot[e] = src[cap + s];
+        t.tt[e] = src[2 * cap + s];
+      }
+    }
+  }
   Stage sg;
   sg.p = sg.q = sg.po = sg.ao = sg.ts = sg.tns = 0;
   sg.k = 0;
@@ -628,14 +815,27 @@ __device__ void run_book(const ProcArgs &a, int i) {
   // int32 apart per listed book
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
                      : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
-  process_all(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
+  process_all<TAIL>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
   flush(st, sg);
-  if (a.l2_mode == 2) write_l2(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
+  if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
   store_chunk(bk.ask.c0, hb, cap, l, st.n[0]);
   store_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0]);
   store_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1]);
   store_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1]);
+  if constexpr (TAIL) {
+    for (int sd = 0; sd < 2; ++sd) {
+      const Tail &t = bk.tl[sd];
+      const int n = st.n[sd];
+      int2 *dst = hb + (int64_t)sd * 3 * cap;
+      for (int s = kSlots + l; s < n; s += kWave) {
+        const int e = n - 1 - s;
+        dst[s] = t.pq[e];
+        dst[cap + s] = t.ot[e];
+        dst[2 * cap + s] = t.tt[e];
+      }
+    }
+  }
   if (st.fills) {
     if (st.fill_count > st.fill_cap) st.flags |= kFlagFillsFull;
     if (l == 0 && a.fill_counts) a.fill_counts[row] = st.fill_count;
@@ -660,11 +860,13 @@ __device__ void run_book(const ProcArgs &a, int i) {
   }
 }
 
+template <bool TAIL>
 __global__ void __launch_bounds__(1024) k_process_small(ProcArgs a) {
+  extern __shared__ int2 tail_smem[];
   const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * a.bpb + w;
   if (i >= a.n) return;
-  run_book(a, i);
+  run_book<TAIL>(a, i, TAIL ? tail_smem + (int64_t)w * a.lds_int2_per_wave : nullptr);
 }
 
 __global__ void k_selftest_shift(int32_t *out) {
@@ -682,11 +884,22 @@ __global__ void k_selftest_shift(int32_t *out) {
 
 int small_book_slots() { return kSlots; }
 
-hipError_t launch_process_small(const ProcArgs &a, hipStream_t s) {
+// tail = false: books of capacity <= 128; tail = true: a.W tail entries per side in
+// LDS (a.lds_int2_per_wave = 6 * a.W per wave)
+hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int threads = a.bpb * kWave;
   const int grid = (a.n + a.bpb - 1) / a.bpb;
-  hipLaunchKernelGGL(k_process_small, dim3(grid), dim3(threads), 0, s, a);
+  if (tail)
+    hipLaunchKernelGGL(k_process_small<true>, dim3(grid), dim3(threads),
+                       (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2), s, a);
+  else
+    hipLaunchKernelGGL(k_process_small<false>, dim3(grid), dim3(threads), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t set_process_small_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute((const void *)k_process_small<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }
 
 hipError_t launch_selftest_shift(int32_t *out, hipStream_t s) {
