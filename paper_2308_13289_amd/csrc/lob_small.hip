@@ -189,11 +189,6 @@ __device__ __forceinline__ void fills_many(State &st, bool takes, int P, int fil
   st.fill_count += popc(ma);
 }
 
-// lanes [0, k) as a mask, k uniform (k <= 0: none, k >= 64: all)
-__device__ __forceinline__ uint64_t lanes_below(int k) {
-  return k >= kWave ? ~0ull : (k <= 0 ? 0ull : (1ull << k) - 1ull);
-}
-
 __device__ __forceinline__ Chunk edge(const Chunk &x, int lane) {  // uniform fields of one lane
   Chunk v;
   v.p = rdlane(x.p, lane);
@@ -332,7 +327,8 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
   const Tail &tl = bk.tl[OPP];
   int n = st.n[OPP];
   constexpr bool buyer = (OPP == 0);
-  if (q <= 0 || n == 0) return q;
+  if (n == 0) return q;
+  if (q <= 0) return q;
   const int bp = rdlane(S.c0.p, 0);
   if (buyer ? bp > lim : bp < lim) return q;  // the best standing price does not overlap
   const int bq = rdlane(S.c0.q, 0);
@@ -408,8 +404,8 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
     return;
   }
   const int nr = n < kSlots ? n : kSlots;
-  int pos = popc(ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P) & lanes_below(nr));
-  if (pos == kWave && nr > kWave) pos += popc(ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P) & lanes_below(nr - kWave));
+  int pos = popc(ballot((l < nr) & (SD == 1 ? S.c0.p >= P : S.c0.p <= P)));
+  if (pos == kWave && nr > kWave) pos += popc(ballot((l + kWave < nr) & (SD == 1 ? S.c1.p >= P : S.c1.p <= P)));
   Chunk v;
   v.p = P;
   v.q = Q;
@@ -486,11 +482,11 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
   const int n = st.n[SD];
   const int nr = n < kSlots ? n : kSlots;
   int k = -1;
-  uint64_t m = ballot(S.c0.o == oid) & lanes_below(nr);
+  uint64_t m = ballot((l < nr) & (S.c0.o == oid));
   if (m) {
     k = first_set(m);
   } else if (nr > kWave) {
-    m = ballot(S.c1.o == oid) & lanes_below(nr - kWave);
+    m = ballot((l + kWave < nr) & (S.c1.o == oid));
     if (m) k = kWave + first_set(m);
   }
   int t = -1;  // TAIL: entry in the tail
@@ -498,11 +494,11 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
     if (k < 0 && n > kSlots) t = tail_find(n - kSlots, [&](int e) { return tl.ot[e].x == oid; });
   }
   if (k < 0 && t < 0) {
-    m = ballot((S.c0.o <= -9000) & (S.c0.p == price)) & lanes_below(nr);
+    m = ballot((l < nr) & (S.c0.o <= -9000) & (S.c0.p == price));
     if (m) {
       k = first_set(m);
     } else if (nr > kWave) {
-      m = ballot((S.c1.o <= -9000) & (S.c1.p == price)) & lanes_below(nr - kWave);
+      m = ballot((l + kWave < nr) & (S.c1.o <= -9000) & (S.c1.p == price));
       if (m) k = kWave + first_set(m);
     }
     if constexpr (TAIL) {
