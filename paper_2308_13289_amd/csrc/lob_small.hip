@@ -659,17 +659,25 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
                                             long long n1, long long beg2, long long n2, int32_t *l2_rows) {
   const int l = lane_id();
   const long long total = n1 + n2;
-#pragma nounroll
-  for (long long k0 = 0; k0 < total; k0 += kWave) {
-    const int cnt = (int)((total - k0) < kWave ? (total - k0) : kWave);
-    int4 u = make_int4(0, 0, 0, 0), v = make_int4(0, 0, 0, 0);
-    if (l < cnt) {
-      const long long k = k0 + l;
+  // record k0 + lane of the stream, loaded one chunk ahead of its use
+  auto fetch = [&](long long k0, int4 &u, int4 &v) {
+    const long long k = k0 + l;
+    if (k < total) {
       const int32_t *rec = k < n1 ? a.msgs + (beg1 + k) * kMsgFields : a.msgs2 + (beg2 + k - n1) * kMsgFields;
       const int4 *mp = reinterpret_cast<const int4 *>(rec);
       u = mp[0];
       v = mp[1];
+    } else {
+      u = v = make_int4(0, 0, 0, 0);
     }
+  };
+  int4 un, vn;
+  fetch(0, un, vn);
+#pragma nounroll
+  for (long long k0 = 0; k0 < total; k0 += kWave) {
+    const int cnt = (int)((total - k0) < kWave ? (total - k0) : kWave);
+    const int4 u = un, v = vn;
+    if (k0 + kWave < total) fetch(k0 + kWave, un, vn);
     const int T = u.x, S = u.y;
     const bool ok = (l < cnt) & (T >= 1) & (T <= 4) & ((S == 1) | (S == -1));
     const int code = !ok ? 0 : (T == 1 ? 1 : T == 4 ? 3 : 5) + (S == 1 ? 1 : 0);
