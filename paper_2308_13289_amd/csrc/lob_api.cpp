@@ -245,6 +245,7 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
     (void)lob::set_process_lds_limit(c->max_lds);
     (void)lob::set_process_unsorted_lds_limit(c->max_lds);
     (void)lob::set_process_small_lds_limit(c->max_lds);
+    (void)hipGetLastError();  // an attribute the platform refuses must not linger as the last error
   }
   if (e != hipSuccess) {
     g_create_error = std::string("context setup: ") + hipGetErrorString(e);
