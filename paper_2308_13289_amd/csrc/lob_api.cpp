@@ -114,7 +114,8 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
       return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
     }
     // the first 128 orders per side in registers, the rest in an LDS tail
-    const int tw = cap_limit - lob::small_book_slots();
+    // tail entries per side, even: the bid side's 16-byte records start 24 * tw bytes in
+    const int tw = (cap_limit - lob::small_book_slots() + 1) & ~1;
     const int per_wave = 6 * tw;
     if ((size_t)per_wave * sizeof(int2) <= c->max_lds) {
       int b = std::max(1, std::min(16, bpb));

@@ -52,7 +52,8 @@ struct Side {
 // entry t of a side holding n orders is slot n - 1 - t -- so orders enter and leave
 // the register window at the tail's end, the only place top-of-book traffic touches.
 struct Tail {
-  int2 *pq, *ot, *tt;
+  int4 *a;  // (P, Q, OID, TID)
+  int2 *b;  // (Ts, Tns)
 };
 
 struct Book {
@@ -69,21 +70,49 @@ __device__ __forceinline__ Side &side(Book &b) {
 }
 
 __device__ __forceinline__ Chunk tail_get(const Tail &t, int i) {
-  const int2 a = t.pq[i], b = t.ot[i], c = t.tt[i];
+  const int4 a = t.a[i];
+  const int2 b = t.b[i];
   Chunk v;
   v.p = a.x;
   v.q = a.y;
-  v.o = b.x;
-  v.t = b.y;
-  v.ts = c.x;
-  v.tns = c.y;
+  v.o = a.z;
+  v.t = a.w;
+  v.ts = b.x;
+  v.tns = b.y;
   return v;
 }
 
 __device__ __forceinline__ void tail_put(const Tail &t, int i, const Chunk &v) {
-  t.pq[i] = make_int2(v.p, v.q);
-  t.ot[i] = make_int2(v.o, v.t);
-  t.tt[i] = make_int2(v.ts, v.tns);
+  t.a[i] = make_int4(v.p, v.q, v.o, v.t);
+  t.b[i] = make_int2(v.ts, v.tns);
+}
+
+// Tail entries [lo, hi) move by d = +1 (up) or -1 (down).  Up to four 64-entry
+// groups are read before any is written, groups taken from the top for a move up
+// and from the bottom for a move down, so every entry is read before the write
+// that lands on it.
+__device__ __forceinline__ void tail_move(const Tail &t, int lo, int hi, int d) {
+  constexpr int G = 4;
+  const int l = lane_id();
+  if (hi <= lo) return;
+  const int span = G * kWave;
+  for (int k = 0; k < hi - lo; k += span) {
+    // this round's entries: [r0, r0 + span) clipped to [lo, hi)
+    const int r0 = d > 0 ? (hi - k - span) : (lo + k);
+    Chunk v[G];
+    bool mv[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = r0 + g * kWave + l;
+      mv[g] = (e >= lo) & (e < hi);
+      if (mv[g]) v[g] = tail_get(t, e);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = r0 + g * kWave + l;
+      if (mv[g]) tail_put(t, e + d, v[g]);
+    }
+  }
 }
 
 __device__ __forceinline__ void pick(Chunk &x, bool c, const Chunk &v) {
@@ -419,23 +448,21 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
       // (equal or better price) are the entries [T - c, T); they move up by one and
       // the new order takes entry T - c.
       const int T = n - kSlots;
+      // the orders ahead form a suffix: count from the top, 64 entries at a time,
+      // until an entry is not ahead
       int c = 0;
-      for (int base = 0; base < T; base += kWave) {
-        const int t = base + l;
+      for (int top = T; top > 0; top -= kWave) {
+        const int t = top - 1 - l;
         bool ahead = false;
-        if (t < T) {
-          const int p = tl.pq[t].x;
+        if (t >= 0) {
+          const int p = tl.a[t].x;
           ahead = SD == 1 ? p >= P : p <= P;
         }
-        c += popc(ballot(ahead));
+        const int k = popc(ballot(ahead));
+        c += k;
+        if (k < kWave) break;
       }
-      for (int base = (T - 1) & ~63; base >= 0 && base + kWave > T - c; base -= kWave) {
-        const int t = base + l;
-        const bool mv = (t >= T - c) & (t < T);
-        Chunk e;
-        if (mv) e = tail_get(tl, t);
-        if (mv) tail_put(tl, t + 1, e);
-      }
+      tail_move(tl, T - c, T, 1);
       if (l == 0) tail_put(tl, T - c, v);
       st.n[SD] = n + 1;
       return;
@@ -491,7 +518,7 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
   }
   int t = -1;  // TAIL: entry in the tail
   if constexpr (TAIL) {
-    if (k < 0 && n > kSlots) t = tail_find(n - kSlots, [&](int e) { return tl.ot[e].x == oid; });
+    if (k < 0 && n > kSlots) t = tail_find(n - kSlots, [&](int e) { return tl.a[e].z == oid; });
   }
   if (k < 0 && t < 0) {
     m = ballot((l < nr) & (S.c0.o <= -9000) & (S.c0.p == price));
@@ -503,7 +530,7 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
     }
     if constexpr (TAIL) {
       if (k < 0 && n > kSlots)
-        t = tail_find(n - kSlots, [&](int e) { return tl.ot[e].x <= -9000 && tl.pq[e].x == price; });
+        t = tail_find(n - kSlots, [&](int e) { return tl.a[e].z <= -9000 && tl.a[e].x == price; });
     }
   }
   if (k < 0 && t < 0) {
@@ -513,21 +540,14 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
   if constexpr (TAIL) {
     if (t >= 0) {
       const int T = n - kSlots;
-      const int2 pq = tl.pq[t];
-      const int P = uni(pq.x), Q = uni(pq.y);
+      const int4 e = tl.a[t];
+      const int P = uni(e.x), Q = uni(e.y);
       st.cancelled_qty += min(qty, Q);
       const int left = Q - qty;
       if (left > 0) {
-        if (l == 0) tl.pq[t] = make_int2(P, left);
+        if (l == 0) tl.a[t] = make_int4(P, left, uni(e.z), uni(e.w));
       } else {
-        // the entries above it (better priority) move down by one
-        for (int base = (t + 1) & ~63; base < T; base += kWave) {
-          const int e = base + l;
-          const bool mv = (e > t) & (e < T);
-          Chunk x;
-          if (mv) x = tail_get(tl, e);
-          if (mv) tail_put(tl, e - 1, x);
-        }
+        tail_move(tl, t + 1, T, -1);  // the entries above it (better priority) move down by one
         st.n[SD] = n - 1;
       }
       return;
@@ -572,14 +592,14 @@ __device__ __forceinline__ void l2_side(const Side &S, const Tail &tl, int n, in
       int next_in = 0;  // the price of slot 64(c+1)
       if (c == 0 && nr > kWave) next_in = rdlane(S.c1.p, 0);
       if constexpr (TAIL) {
-        if (c == 1 && n > kSlots) next_in = uni(tl.pq[n - kSlots - 1].x);
+        if (c == 1 && n > kSlots) next_in = uni(tl.a[n - kSlots - 1].x);
       }
       next = shl1(p, next_in);
     } else {
       // slot s is tail entry n - 1 - s
-      p = valid ? tl.pq[n - 1 - s].x : 0;
-      q = valid ? tl.pq[n - 1 - s].y : 0;
-      next = (s + 1 < n) ? tl.pq[n - 2 - s].x : 0;
+      p = valid ? tl.a[n - 1 - s].x : 0;
+      q = valid ? tl.a[n - 1 - s].y : 0;
+      next = (s + 1 < n) ? tl.a[n - 2 - s].x : 0;
     }
     const bool is_last = valid & ((s + 1 == n) | (next != p));
     const int incl = q_before + scan_incl(valid ? q : 0);
@@ -784,16 +804,15 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     // slot s >= 128 of a side holding n orders is tail entry n - 1 - s
     for (int sd = 0; sd < 2; ++sd) {
       Tail &t = bk.tl[sd];
-      t.pq = lds + (sd * 3 + 0) * a.W;
-      t.ot = lds + (sd * 3 + 1) * a.W;
-      t.tt = lds + (sd * 3 + 2) * a.W;
+      t.a = reinterpret_cast<int4 *>(lds + sd * 3 * a.W);  // 16-byte aligned: a.W int4 = 2 a.W int2
+      t.b = lds + sd * 3 * a.W + 2 * a.W;
       const int n = st.n[sd];
       const int2 *src = hb + (int64_t)sd * 3 * cap;
       for (int s = kSlots + l; s < n; s += kWave) {
         const int e = n - 1 - s;
-        t.pq[e] = src[s];
-        t.ot[e] = src[cap + s];
-        t.tt[e] = src[2 * cap + s];
+        const int2 pq = src[s], ot = src[cap + s];
+        t.a[e] = make_int4(pq.x, pq.y, ot.x, ot.y);
+        t.b[e] = src[2 * cap + s];
       }
     }
   }
@@ -834,9 +853,10 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
       int2 *dst = hb + (int64_t)sd * 3 * cap;
       for (int s = kSlots + l; s < n; s += kWave) {
         const int e = n - 1 - s;
-        dst[s] = t.pq[e];
-        dst[cap + s] = t.ot[e];
-        dst[2 * cap + s] = t.tt[e];
+        const int4 v = t.a[e];
+        dst[s] = make_int2(v.x, v.y);
+        dst[cap + s] = make_int2(v.z, v.w);
+        dst[2 * cap + s] = t.b[e];
       }
     }
   }
@@ -866,7 +886,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
 
 template <bool TAIL>
 __global__ void __launch_bounds__(1024) k_process_small(ProcArgs a) {
-  extern __shared__ int2 tail_smem[];
+  extern __shared__ __align__(16) int2 tail_smem[];
   const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * a.bpb + w;
   if (i >= a.n) return;
