@@ -394,6 +394,11 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
   lob::ProcArgs a = lob::base_args(ctx, d_ids, (int32_t)small.size());
   a.msgs = msgs;
   a.ranges = d_ranges;
+  {
+    int64_t longest = 0;
+    for (int32_t i = 0; i < n_books; ++i) longest = std::max<int64_t>(longest, len(i));
+    a.prio_len = std::max<int64_t>(1, longest / 2);
+  }
   a.out_rows = d_rows;
   a.l2_mode = l2_mode;
   a.l2_out = l2_out;

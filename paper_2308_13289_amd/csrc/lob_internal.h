@@ -73,6 +73,10 @@ struct ProcArgs {
   // (L2 / fills row of listed book i); nullptr = offs / identity
   const int64_t *ranges;
   const int32_t *out_rows;
+  // a wave whose book has at least this many source-1 messages raises its issue
+  // priority (0: none); ragged calls set it so the longest streams, the critical
+  // path, are not slowed by the short ones sharing their compute unit
+  int64_t prio_len;
 };
 
 }  // namespace lob

@@ -834,6 +834,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     }
   }
   const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
+  if (a.prio_len > 0 && n1 >= a.prio_len) __builtin_amdgcn_s_setprio(3);
   // per-message L2 rows of source 1: contiguous by message index, or l2_stride
   // int32 apart per listed book
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
