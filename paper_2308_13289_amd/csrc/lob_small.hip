@@ -130,8 +130,18 @@ struct Stage {
   int k;
 };
 
+// Sum over the wave of a non-negative int32 per lane, as 64-bit.
+__device__ __forceinline__ long long wave_sum(int v) {
+  const int lo = scan_incl(v & 0xffff);
+  const int hi = scan_incl((int)((unsigned)v >> 16));
+  return (long long)rdlane(lo, 63) + ((long long)rdlane(hi, 63) << 16);
+}
+
+// The pending trades are counted (trades and traded quantity) and stored.
 __device__ __forceinline__ void flush(State &st, Stage &sg) {
   if (sg.k == 0) return;
+  st.n_trades += sg.k;
+  st.traded_qty += wave_sum(lane_id() < sg.k ? sg.q : 0);
   if (st.log) {
     const long long room = st.log_cap - st.log_count;
     const int stored = room < sg.k ? (room > 0 ? (int)room : 0) : sg.k;
@@ -349,7 +359,9 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 
 // Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
 // with limit price lim and quantity q.  Returns the unfilled quantity.
-template <int OPP, bool TAIL>
+// EXTRA: the launch collects agent fills or per-message L2 (else those checks are
+// compiled out).
+template <int OPP, bool TAIL, bool EXTRA>
 __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, int q, int a_oid, int a_tid, int ts,
                                      int tns) {
   Side &S = side<OPP>(bk);
@@ -365,9 +377,7 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
     // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
     const int bo = rdlane(S.c0.o, 0);
     stage_one(st, sg, bp, q, bo, a_oid, ts, tns);
-    if (st.fills) fills_one(st, bp, q, bo, a_oid, ts, tns, rdlane(S.c0.t, 0), a_tid);
-    st.traded_qty += q;
-    st.n_trades++;
+    if (EXTRA && st.fills) fills_one(st, bp, q, bo, a_oid, ts, tns, rdlane(S.c0.t, 0), a_tid);
     if (q < bq) {
       S.c0.q = wl(S.c0.q, bq - q, 0);
     } else {
@@ -400,11 +410,9 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
       const int nfull = popc(ballot(full));
       const int fill = takes ? min(qv, q - excl) : 0;
       stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
-      fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
+      if constexpr (EXTRA) fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
       F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
       const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
-      st.traded_qty += consumed;
-      st.n_trades += ntr;
       q -= consumed;
       removed += nfull;
       if (nfull < kWave) break;
@@ -630,51 +638,52 @@ __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L,
 // price 0 (sell) / max_int (buy), drop the rest (item 3); cancel and delete are
 // the same operation (item 2).  One straight call sequence per case, so that no
 // flag derived from the case has to survive across branches.
-template <bool TAIL>
-__device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, int P, int Q, int oid, int tid,
-                                            int ts, int tns) {
+// Message j of the chunk held as u = (type, side, P, Q), v = (oid, tid, ts, tns)
+// across the lanes; each case reads only the fields it uses.
+template <bool TAIL, bool EXTRA>
+__device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, const int4 &u, const int4 &v,
+                                            int j) {
   switch (code) {
     case 1: {
-      const int rem = match<1, TAIL>(bk, st, sg, P, Q, oid, tid, ts, tns);
+      const int P = rdlane(u.z, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j),
+                tns = rdlane(v.w, j);
+      const int rem = match<1, TAIL, EXTRA>(bk, st, sg, P, rdlane(u.w, j), oid, tid, ts, tns);
       if (rem > 0) insert<0, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
       break;
     }
     case 2: {
-      const int rem = match<0, TAIL>(bk, st, sg, P, Q, oid, tid, ts, tns);
+      const int P = rdlane(u.z, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j),
+                tns = rdlane(v.w, j);
+      const int rem = match<0, TAIL, EXTRA>(bk, st, sg, P, rdlane(u.w, j), oid, tid, ts, tns);
       if (rem > 0) insert<1, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
       break;
     }
     case 3: {
-      const int rem = match<1, TAIL>(bk, st, sg, 0, Q, oid, tid, ts, tns);
+      const int rem = match<1, TAIL, EXTRA>(bk, st, sg, 0, rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j),
+                                            rdlane(v.z, j), rdlane(v.w, j));
       if (rem > 0) st.market_discarded += rem;
       break;
     }
     case 4: {
-      const int rem = match<0, TAIL>(bk, st, sg, INT_MAX, Q, oid, tid, ts, tns);
+      const int rem = match<0, TAIL, EXTRA>(bk, st, sg, INT_MAX, rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j),
+                                            rdlane(v.z, j), rdlane(v.w, j));
       if (rem > 0) st.market_discarded += rem;
       break;
     }
     case 5:
-      cancel<0, TAIL>(bk, st, oid, Q, P);
+      cancel<0, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
       break;
     case 6:
-      cancel<1, TAIL>(bk, st, oid, Q, P);
+      cancel<1, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
       break;
     default:
       break;
   }
 }
 
-// Sum over the wave of a non-negative int32 per lane, as 64-bit.
-__device__ __forceinline__ long long wave_sum(int v) {
-  const int lo = scan_incl(v & 0xffff);
-  const int hi = scan_incl((int)((unsigned)v >> 16));
-  return (long long)rdlane(lo, 63) + ((long long)rdlane(hi, 63) << 16);
-}
-
 // The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
 // form's agent orders) msgs2[beg2, beg2 + n2), in 64-message chunks.
-template <bool TAIL>
+template <bool TAIL, bool EXTRA>
 __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, const ProcArgs &a, long long beg1,
                                             long long n1, long long beg2, long long n2, int32_t *l2_rows) {
   const int l = lane_id();
@@ -727,9 +736,10 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
 #pragma nounroll
     for (int j = 0; j < cnt; ++j) {
       const int c = rdlane(code, j);
-      process_msg<TAIL>(bk, st, sg, c, rdlane(u.z, j), rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j), rdlane(v.z, j),
-                  rdlane(v.w, j));
-      if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+      process_msg<TAIL, EXTRA>(bk, st, sg, c, u, v, j);
+      if constexpr (EXTRA) {
+        if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+      }
     }
   }
 }
@@ -757,7 +767,7 @@ __device__ __forceinline__ void store_chunk(const Chunk &x, int2 *base, int cap,
 }
 
 // TAIL form: tails of the two sides in LDS at `lds`, a.W entries each.
-template <bool TAIL>
+template <bool TAIL, bool EXTRA>
 __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   const int l = lane_id();
   const int book = a.book_ids ? uni(a.book_ids[i]) : i;
@@ -839,7 +849,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   // int32 apart per listed book
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
                      : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
-  process_all<TAIL>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
+  process_all<TAIL, EXTRA>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
   flush(st, sg);
   if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
@@ -885,13 +895,13 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   }
 }
 
-template <bool TAIL>
+template <bool TAIL, bool EXTRA>
 __global__ void __launch_bounds__(1024) k_process_small(ProcArgs a) {
   extern __shared__ __align__(16) int2 tail_smem[];
   const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * a.bpb + w;
   if (i >= a.n) return;
-  run_book<TAIL>(a, i, TAIL ? tail_smem + (int64_t)w * a.lds_int2_per_wave : nullptr);
+  run_book<TAIL, EXTRA>(a, i, TAIL ? tail_smem + (int64_t)w * a.lds_int2_per_wave : nullptr);
 }
 
 __global__ void k_selftest_shift(int32_t *out) {
@@ -914,16 +924,24 @@ int small_book_slots() { return kSlots; }
 hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int threads = a.bpb * kWave;
   const int grid = (a.n + a.bpb - 1) / a.bpb;
-  if (tail)
-    hipLaunchKernelGGL(k_process_small<true>, dim3(grid), dim3(threads),
-                       (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2), s, a);
+  const size_t lds = tail ? (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2) : 0;
+  const bool extra = a.fills != nullptr || a.l2_mode == 1;
+  if (tail && extra)
+    hipLaunchKernelGGL((k_process_small<true, true>), dim3(grid), dim3(threads), lds, s, a);
+  else if (tail)
+    hipLaunchKernelGGL((k_process_small<true, false>), dim3(grid), dim3(threads), lds, s, a);
+  else if (extra)
+    hipLaunchKernelGGL((k_process_small<false, true>), dim3(grid), dim3(threads), 0, s, a);
   else
-    hipLaunchKernelGGL(k_process_small<false>, dim3(grid), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((k_process_small<false, false>), dim3(grid), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t set_process_small_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute((const void *)k_process_small<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void *)k_process_small<true, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_process_small<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)bytes);
 }
 
