@@ -33,6 +33,15 @@ using namespace dev;
 
 constexpr int kSlots = 2 * kWave;  // orders per side the kernel holds
 
+// Branch-layout hints: the expected outcome becomes the fall-through path.
+#define LOB_LIKELY(x) __builtin_expect(!!(x), 1)
+#define LOB_UNLIKELY(x) __builtin_expect(!!(x), 0)
+
+// Wait for the wave's outstanding LDS operations (lgkmcnt 0; vmcnt, expcnt left at
+// their maxima), so that results of a ds_bpermute are in place before the next
+// message instead of being waited for at every later use.
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xc07f); }
+
 // x with lane `lane` (uniform) replaced by the uniform value v
 __device__ __forceinline__ int wl(int x, int v, int lane) { return lob_writelane_i32(v, lane, x); }
 // lane l receives lane l-1 (up1) or l+1 (dn1); the lane without a source receives 0
@@ -166,7 +175,7 @@ __device__ __forceinline__ void stage_one(State &st, Stage &sg, int P, int fill,
   sg.ao = wl(sg.ao, ao, sg.k);
   sg.ts = wl(sg.ts, ts, sg.k);
   sg.tns = wl(sg.tns, tns, sg.k);
-  if (++sg.k == kWave) flush(st, sg);
+  if (LOB_UNLIKELY(++sg.k == kWave)) flush(st, sg);
 }
 
 // ntr trades held by lanes [0, ntr) (P, fill, passive id per lane; the aggressor
@@ -328,6 +337,7 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
     S.c0.t = from_lane(S.c0.t, src);
     S.c0.ts = from_lane(S.c0.ts, src);
     S.c0.tns = from_lane(S.c0.tns, src);
+    lds_wait();
     return;
   }
   Chunk a, b;
@@ -355,25 +365,27 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
   } else {
     S.c0 = b;  // slot l takes slot 64 + (l + m - 64)
   }
+  lds_wait();
 }
 
 // Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
 // with limit price lim and quantity q.  Returns the unfilled quantity.
 // EXTRA: the launch collects agent fills or per-message L2 (else those checks are
-// compiled out).
-template <int OPP, bool TAIL, bool EXTRA>
+// compiled out).  LIMIT: a limit order, which more often than not rests untouched
+// (a layout hint only).
+template <int OPP, bool TAIL, bool EXTRA, bool LIMIT>
 __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, int q, int a_oid, int a_tid, int ts,
                                      int tns) {
   Side &S = side<OPP>(bk);
   const Tail &tl = bk.tl[OPP];
   int n = st.n[OPP];
   constexpr bool buyer = (OPP == 0);
-  if (n == 0) return q;
-  if (q <= 0) return q;
+  if (LOB_UNLIKELY(n == 0)) return q;  // q > 0: the decode turns messages with Q <= 0 into no-ops
   const int bp = rdlane(S.c0.p, 0);
-  if (buyer ? bp > lim : bp < lim) return q;  // the best standing price does not overlap
+  const bool apart = buyer ? bp > lim : bp < lim;  // the best standing price does not overlap
+  if (LIMIT ? LOB_LIKELY(apart) : LOB_UNLIKELY(apart)) return q;
   const int bq = rdlane(S.c0.q, 0);
-  if (q <= bq) {
+  if (LOB_LIKELY(q <= bq)) {
     // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
     const int bo = rdlane(S.c0.o, 0);
     stage_one(st, sg, bp, q, bo, a_oid, ts, tns);
@@ -398,16 +410,18 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
       if (c == 1 && (removed < kWave || nr <= kWave || q == 0)) break;
       Chunk &F = c == 0 ? S.c0 : S.c1;
       const bool valid = c * kWave + l < nr;
-      const bool cross = valid & (buyer ? F.p <= lim : F.p >= lim);
+      const bool at = buyer ? F.p <= lim : F.p >= lim;
+      const uint64_t mc = ballot(valid) & ballot(at);
+      const bool cross = valid & at;
       const int qv = cross ? F.q : 0;
       const int incl = scan_incl(qv);
       const int excl = incl - qv;
       const bool takes = cross & (excl < q);
-      const uint64_t mt = ballot(takes);
+      const uint64_t mt = mc & ballot(excl < q);
       if (mt == 0) break;
       const int ntr = popc(mt);
       const bool full = cross & (incl <= q);
-      const int nfull = popc(ballot(full));
+      const int nfull = popc(mc & ballot(incl <= q));
       const int fill = takes ? min(qv, q - excl) : 0;
       stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
       if constexpr (EXTRA) fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
@@ -435,14 +449,16 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
   const int n = st.n[SD];
-  if (n >= st.cap) {
-    st.rejected_qty += Q;
+  if (LOB_UNLIKELY(n >= st.cap)) {
+    st.rejected_qty += (unsigned)Q;
     st.flags |= kFlagSideFull;
     return;
   }
   const int nr = n < kSlots ? n : kSlots;
-  int pos = popc(ballot((l < nr) & (SD == 1 ? S.c0.p >= P : S.c0.p <= P)));
-  if (pos == kWave && nr > kWave) pos += popc(ballot((l + kWave < nr) & (SD == 1 ? S.c1.p >= P : S.c1.p <= P)));
+  // the orders ahead (price equal or better) form a prefix, so chunk 1 holds some
+  // only when chunk 0 is all ahead: both counts add up without a test
+  const int pos = popc(ballot(l < nr) & ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P)) +
+                  popc(ballot(l + kWave < nr) & ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P));
   Chunk v;
   v.p = P;
   v.q = Q;
@@ -481,12 +497,15 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
       if (l == 0) tail_put(tl, n - kSlots, last);
     }
   }
-  if (nr >= kWave) {  // chunk 1 changes: slot 63 moves into slot 64, or the new order lands there
+  // (without a tail a side rarely holds 64 orders or more: chunk 1 work is laid out
+  // of line)
+  if (TAIL ? (nr >= kWave) : LOB_UNLIKELY(nr >= kWave)) {
+    // chunk 1 changes: slot 63 moves into slot 64, or the new order lands there
     const Chunk in = edge(S.c0, 63);
     shift_up(S.c1, l + kWave > pos);
     if (pos < kWave) put(S.c1, in, 0);
   }
-  if (pos < kWave) {
+  if (TAIL ? (pos < kWave) : LOB_LIKELY(pos < kWave)) {
     shift_up(S.c0, l > pos);
     put(S.c0, v, pos);
   } else {
@@ -510,18 +529,28 @@ __device__ __forceinline__ int tail_find(int T, Pred pred) {
 // Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders) on side SD.
 template <int SD, bool TAIL>
 __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, int price) {
-  if (qty <= 0) return;
   Side &S = side<SD>(bk);
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
   const int n = st.n[SD];
   const int nr = n < kSlots ? n : kSlots;
   int k = -1;
-  uint64_t m = ballot((l < nr) & (S.c0.o == oid));
-  if (m) {
-    k = first_set(m);
-  } else if (nr > kWave) {
-    m = ballot((l + kWave < nr) & (S.c1.o == oid));
+  uint64_t m = ballot(l < nr) & ballot(S.c0.o == oid);
+  if (LOB_LIKELY(m != 0)) {
+    // the common case, an order in chunk 0 found by its id
+    const int k0 = first_set(m);
+    const int Q = rdlane(S.c0.q, k0);
+    st.cancelled_qty += (unsigned)min(qty, Q);
+    if (LOB_LIKELY(Q > qty)) {
+      S.c0.q = wl(S.c0.q, Q - qty, k0);
+    } else {
+      remove_at<TAIL>(S, tl, k0, n);
+      st.n[SD] = n - 1;
+    }
+    return;
+  }
+  if (nr > kWave) {
+    m = ballot(l + kWave < nr) & ballot(S.c1.o == oid);
     if (m) k = kWave + first_set(m);
   }
   int t = -1;  // TAIL: entry in the tail
@@ -529,11 +558,11 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
     if (k < 0 && n > kSlots) t = tail_find(n - kSlots, [&](int e) { return tl.a[e].z == oid; });
   }
   if (k < 0 && t < 0) {
-    m = ballot((l < nr) & (S.c0.o <= -9000) & (S.c0.p == price));
+    m = ballot(l < nr) & ballot(S.c0.o <= -9000) & ballot(S.c0.p == price);
     if (m) {
       k = first_set(m);
     } else if (nr > kWave) {
-      m = ballot((l + kWave < nr) & (S.c1.o <= -9000) & (S.c1.p == price));
+      m = ballot(l + kWave < nr) & ballot(S.c1.o <= -9000) & ballot(S.c1.p == price);
       if (m) k = kWave + first_set(m);
     }
     if constexpr (TAIL) {
@@ -564,7 +593,7 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
   const bool lo = k < kWave;
   const int kl = k & 63;
   const int Q = lo ? rdlane(S.c0.q, kl) : rdlane(S.c1.q, kl);
-  st.cancelled_qty += min(qty, Q);
+  st.cancelled_qty += (unsigned)min(qty, Q);
   const int left = Q - qty;
   if (left > 0) {
     if (lo)
@@ -643,41 +672,30 @@ __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L,
 template <bool TAIL, bool EXTRA>
 __device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, const int4 &u, const int4 &v,
                                             int j) {
-  switch (code) {
-    case 1: {
-      const int P = rdlane(u.z, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j),
-                tns = rdlane(v.w, j);
-      const int rem = match<1, TAIL, EXTRA>(bk, st, sg, P, rdlane(u.w, j), oid, tid, ts, tns);
+  // tested in order of frequency: limit orders, cancels, market orders
+  if (LOB_LIKELY((unsigned)(code - 1) < 2u)) {
+    const int P = rdlane(u.z, j), Q = rdlane(u.w, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j),
+              ts = rdlane(v.z, j), tns = rdlane(v.w, j);
+    __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 0
+    if (code == 1) {
+      const int rem = match<1, TAIL, EXTRA, true>(bk, st, sg, P, Q, oid, tid, ts, tns);
       if (rem > 0) insert<0, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
-      break;
-    }
-    case 2: {
-      const int P = rdlane(u.z, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j),
-                tns = rdlane(v.w, j);
-      const int rem = match<0, TAIL, EXTRA>(bk, st, sg, P, rdlane(u.w, j), oid, tid, ts, tns);
+    } else {
+      const int rem = match<0, TAIL, EXTRA, true>(bk, st, sg, P, Q, oid, tid, ts, tns);
       if (rem > 0) insert<1, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
-      break;
     }
-    case 3: {
-      const int rem = match<1, TAIL, EXTRA>(bk, st, sg, 0, rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j),
-                                            rdlane(v.z, j), rdlane(v.w, j));
-      if (rem > 0) st.market_discarded += rem;
-      break;
-    }
-    case 4: {
-      const int rem = match<0, TAIL, EXTRA>(bk, st, sg, INT_MAX, rdlane(u.w, j), rdlane(v.x, j), rdlane(v.y, j),
-                                            rdlane(v.z, j), rdlane(v.w, j));
-      if (rem > 0) st.market_discarded += rem;
-      break;
-    }
-    case 5:
+  } else if (code >= 5) {
+    if (code == 5)
       cancel<0, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
-      break;
-    case 6:
+    else
       cancel<1, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
-      break;
-    default:
-      break;
+  } else if (code != 0) {
+    const int Q = rdlane(u.w, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j),
+              tns = rdlane(v.w, j);
+    __builtin_assume(Q > 0);
+    const int rem = code == 3 ? match<1, TAIL, EXTRA, false>(bk, st, sg, 0, Q, oid, tid, ts, tns)
+                              : match<0, TAIL, EXTRA, false>(bk, st, sg, INT_MAX, Q, oid, tid, ts, tns);
+    if (rem > 0) st.market_discarded += (unsigned)rem;
   }
 }
 
@@ -709,7 +727,9 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
     if (k0 + kWave < total) fetch(k0 + kWave, un, vn);
     const int T = u.x, S = u.y;
     const bool ok = (l < cnt) & (T >= 1) & (T <= 4) & ((S == 1) | (S == -1));
-    const int code = !ok ? 0 : (T == 1 ? 1 : T == 4 ? 3 : 5) + (S == 1 ? 1 : 0);
+    // code 0 also for Q <= 0: such a cancel removes nothing and such a limit or
+    // market order neither trades nor rests; only the counts and the time check see it
+    const int code = !(ok & (u.w > 0)) ? 0 : (T == 1 ? 1 : T == 4 ? 3 : 5) + (S == 1 ? 1 : 0);
     const uint64_t vmask = ballot(ok);
     if (vmask) {
       // times of valid messages must not decrease: compare with the previous valid
