@@ -35,6 +35,11 @@ def command(out):
             "-mllvm", "-structurizecfg-skip-uniform-regions=true",
             # the execution reward is float64 arithmetic in a fixed order: no fused ops
             "-ffp-contract=off",
+            # block layout for the matchers' many short uniform branches: I-cache aware
+            # placement and more tail duplication (more fall-through paths)
+            "-mllvm", "-enable-ext-tsp-block-placement",
+            "-mllvm", "-tail-dup-placement-threshold=16", "-mllvm", "-tail-dup-size=16",
+            "-mllvm", "-tail-dup-placement-aggressive-threshold=16",
             "-Wall", "-Wno-unused-function",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             # the host-only sources go in as HIP too: a "-x c++" input makes hipcc
