@@ -113,10 +113,10 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
       hipError_t e = lob::launch_process_small(a, false, s);
       return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
     }
-    // the first 128 orders per side in registers, the rest in an LDS tail
-    // tail entries per side, even: the bid side's 16-byte records start 24 * tw bytes in
+    // the first 128 orders per side in registers, the rest in an LDS tail of
+    // 16-byte entries (P, Q, OID, handle), tw per side
     const int tw = (cap_limit - lob::small_book_slots() + 1) & ~1;
-    const int per_wave = 6 * tw;
+    const int per_wave = 4 * tw;
     if ((size_t)per_wave * sizeof(int2) <= c->max_lds) {
       int b = std::max(1, std::min(16, bpb));
       while (b > 1 && (size_t)b * per_wave * sizeof(int2) > c->max_lds) --b;
@@ -150,6 +150,7 @@ ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n) {
   std::memset(&a, 0, sizeof(a));
   a.hdr = c->d_hdr;
   a.books = c->d_books;
+  a.books_half = c->books_half;
   a.log = c->d_log;
   a.book_ids = ids;
   a.n = n;
@@ -224,8 +225,9 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
     return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess;
   };
   c->stage_bytes = sizeof(int32_t) * 2 * (size_t)c->n_books + sizeof(int64_t) * 2 * (size_t)c->n_books + 256;
+  c->books_half = book_int2;
   bool ok = alloc((void **)&c->d_hdr, sizeof(lob::BookHdr) * hdr.size()) &&
-            alloc((void **)&c->d_books, sizeof(int2) * (size_t)book_int2) &&
+            alloc((void **)&c->d_books, sizeof(int2) * 2 * (size_t)book_int2) &&
             alloc((void **)&c->d_log, sizeof(int32_t) * lob::kTradeFields * (size_t)log_rec) &&
             alloc((void **)&c->d_stage, c->stage_bytes) &&
             alloc((void **)&c->d_exec_acts, sizeof(int32_t) * 4 * 8 * (size_t)c->n_books) &&

@@ -49,7 +49,8 @@ struct lob_ctx {
   int n_books = 0, L = 10, max_cap = 0;
   std::vector<int32_t> caps;
   lob::BookHdr *d_hdr = nullptr;
-  int2 *d_books = nullptr;
+  int2 *d_books = nullptr;  // two buffers per book, books_half int2 apart
+  int64_t books_half = 0;
   int32_t *d_log = nullptr;
   lob_plan plan{};
   std::string err;

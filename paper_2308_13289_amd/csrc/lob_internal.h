@@ -2,11 +2,15 @@
 //
 // Device memory of a context:
 //   hdr   [n_books] BookHdr           counters, live counts, where the book's arrays are
-//   books [sum 6*cap] int2            per book, per side s (0 asks, 1 bids), three pair
+//   books [2][sum 6*cap] int2         per book, per side s (0 asks, 1 bids), three pair
 //                                     arrays of `cap` entries each, kept in price-time
 //                                     priority (slot 0 = best):  (P, Q), (OID, TID),
 //                                     (Ts, Tns)  -- the six order features of the paper's
-//                                     Section 4, two per 8-byte word
+//                                     Section 4, two per 8-byte word.  Two buffers per
+//                                     book, `books_half` int2 apart: the header's
+//                                     book_off names the current one; the register
+//                                     kernel writes its result to the other and
+//                                     switches book_off, the other kernels work in place
 //   log   [sum log_cap][6] int32      per book, the trade records not yet read
 #pragma once
 #include <stdint.h>
@@ -28,7 +32,7 @@ struct alignas(16) BookHdr {
   int32_t n[2];  // live orders: [0] asks, [1] bids
   int32_t cap;   // capacity per side
   int32_t flags;
-  int64_t book_off;   // first int2 of this book's arrays in `books`
+  int64_t book_off;   // first int2 of this book's current arrays in `books`
   int64_t log_off;    // first record of this book's trade log
   int64_t log_cap;    // records the log can hold
   int64_t log_count;  // records waiting in the log
@@ -44,6 +48,7 @@ static_assert(sizeof(BookHdr) == 144, "BookHdr layout");
 struct ProcArgs {
   BookHdr *hdr;
   int2 *books;
+  int64_t books_half;  // int2 between a book's two buffers
   int32_t *log;        // trade log base, or nullptr: do not log trades
   const int32_t *book_ids;  // nullptr: listed book i is book i
   int32_t n;                // listed books

@@ -3,8 +3,12 @@
 // Same algorithm and results as lob_kernels.hip (one wavefront per book, each side
 // kept in price-time priority, slot 0 = best), different residency: while the
 // book's messages run, the whole book lives in VGPRs.  Side s is two 64-lane
-// chunks (slot 64c + lane in chunk c) of six registers each, one per order field
-// (P, Q, OID, TID, Ts, Tns of Section 4).  The best order is lane 0 of chunk 0;
+// chunks (slot 64c + lane in chunk c) of four registers each: P, Q, OID of
+// Section 4 and a handle H to the order's other fields (TID, Ts, Tns), which only
+// the stored book needs -- the index of the message that added the order in this
+// launch, or the order's slot in the book as loaded.  The book is read from one
+// of its two buffers and written to the other, so the loaded copy stays readable
+// until the end.  The best order is lane 0 of chunk 0;
 // changing one order is a lane-select; moving orders by one slot is a DPP wave
 // shift (wave_shr:1 / wave_shl:1) with the neighbouring chunk's edge lane carried
 // in, and chunk 1 is left alone while the side holds at most 64 orders; removing
@@ -48,9 +52,11 @@ __device__ __forceinline__ int wl(int x, int v, int lane) { return lob_writelane
 __device__ __forceinline__ int up1(int x) { return __builtin_amdgcn_mov_dpp(x, 0x138, 0xf, 0xf, true); }
 __device__ __forceinline__ int dn1(int x) { return __builtin_amdgcn_mov_dpp(x, 0x130, 0xf, 0xf, true); }
 
-// One chunk: the six fields of slots 64c + lane.
+// One chunk: the fields of slots 64c + lane.  h: 2 * k for the order added by
+// message k of this launch's stream, 2 * (-1 - s) for the order loaded from slot s;
+// bit 0 set when the order carries the agent's trader id (step form).
 struct Chunk {
-  int p, q, o, t, ts, tns;
+  int p, q, o, h;
 };
 
 struct Side {
@@ -61,8 +67,7 @@ struct Side {
 // entry t of a side holding n orders is slot n - 1 - t -- so orders enter and leave
 // the register window at the tail's end, the only place top-of-book traffic touches.
 struct Tail {
-  int4 *a;  // (P, Q, OID, TID)
-  int2 *b;  // (Ts, Tns)
+  int4 *a;  // (P, Q, OID, H)
 };
 
 struct Book {
@@ -80,20 +85,16 @@ __device__ __forceinline__ Side &side(Book &b) {
 
 __device__ __forceinline__ Chunk tail_get(const Tail &t, int i) {
   const int4 a = t.a[i];
-  const int2 b = t.b[i];
   Chunk v;
   v.p = a.x;
   v.q = a.y;
   v.o = a.z;
-  v.t = a.w;
-  v.ts = b.x;
-  v.tns = b.y;
+  v.h = a.w;
   return v;
 }
 
 __device__ __forceinline__ void tail_put(const Tail &t, int i, const Chunk &v) {
-  t.a[i] = make_int4(v.p, v.q, v.o, v.t);
-  t.b[i] = make_int2(v.ts, v.tns);
+  t.a[i] = make_int4(v.p, v.q, v.o, v.h);
 }
 
 // Tail entries [lo, hi) move by d = +1 (up) or -1 (down).  Up to four 64-entry
@@ -128,9 +129,7 @@ __device__ __forceinline__ void pick(Chunk &x, bool c, const Chunk &v) {
   x.p = c ? v.p : x.p;
   x.q = c ? v.q : x.q;
   x.o = c ? v.o : x.o;
-  x.t = c ? v.t : x.t;
-  x.ts = c ? v.ts : x.ts;
-  x.tns = c ? v.tns : x.tns;
+  x.h = c ? v.h : x.h;
 }
 
 // Pending trade records, one per lane; k of them (uniform) are pending.
@@ -209,9 +208,9 @@ __device__ __forceinline__ void stage_many(State &st, Stage &sg, int ntr, int P,
 }
 
 // Agent fills (step form): trades where either side carries the agent's trader id.
-__device__ __forceinline__ void fills_one(State &st, int P, int fill, int po, int ao, int ts, int tns, int ptid,
+__device__ __forceinline__ void fills_one(State &st, int P, int fill, int po, int ao, int ts, int tns, bool pag,
                                           int atid) {
-  if (!st.fills || (ptid != st.agent_tid && atid != st.agent_tid)) return;
+  if (!st.fills || (!pag && atid != st.agent_tid)) return;
   if (st.fill_count < st.fill_cap && lane_id() == 0) {
     int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)st.fill_count * kTradeFields);
     r[0] = make_int2(P, fill);
@@ -222,9 +221,9 @@ __device__ __forceinline__ void fills_one(State &st, int P, int fill, int po, in
 }
 
 __device__ __forceinline__ void fills_many(State &st, bool takes, int P, int fill, int po, int ao, int ts, int tns,
-                                           int ptid, int atid) {
+                                           bool pag, int atid) {
   if (!st.fills) return;
-  const bool ag = takes & ((ptid == st.agent_tid) | (atid == st.agent_tid));
+  const bool ag = takes & (pag | (atid == st.agent_tid));
   const uint64_t ma = ballot(ag);
   if (ma == 0) return;
   const int k = st.fill_count + popc(ma & mask_lt());
@@ -242,9 +241,7 @@ __device__ __forceinline__ Chunk edge(const Chunk &x, int lane) {  // uniform fi
   v.p = rdlane(x.p, lane);
   v.q = rdlane(x.q, lane);
   v.o = rdlane(x.o, lane);
-  v.t = rdlane(x.t, lane);
-  v.ts = rdlane(x.ts, lane);
-  v.tns = rdlane(x.tns, lane);
+  v.h = rdlane(x.h, lane);
   return v;
 }
 
@@ -252,23 +249,19 @@ __device__ __forceinline__ Chunk edge(const Chunk &x, int lane) {  // uniform fi
 // Every lane computes the moved value before the select: a DPP move inside a
 // divergent branch would read inactive source lanes.
 __device__ __forceinline__ void shift_dn(Chunk &x, bool take) {
-  const int p = dn1(x.p), q = dn1(x.q), o = dn1(x.o), t = dn1(x.t), ts = dn1(x.ts), tns = dn1(x.tns);
+  const int p = dn1(x.p), q = dn1(x.q), o = dn1(x.o), h = dn1(x.h);
   x.p = take ? p : x.p;
   x.q = take ? q : x.q;
   x.o = take ? o : x.o;
-  x.t = take ? t : x.t;
-  x.ts = take ? ts : x.ts;
-  x.tns = take ? tns : x.tns;
+  x.h = take ? h : x.h;
 }
 
 __device__ __forceinline__ void shift_up(Chunk &x, bool take) {
-  const int p = up1(x.p), q = up1(x.q), o = up1(x.o), t = up1(x.t), ts = up1(x.ts), tns = up1(x.tns);
+  const int p = up1(x.p), q = up1(x.q), o = up1(x.o), h = up1(x.h);
   x.p = take ? p : x.p;
   x.q = take ? q : x.q;
   x.o = take ? o : x.o;
-  x.t = take ? t : x.t;
-  x.ts = take ? ts : x.ts;
-  x.tns = take ? tns : x.tns;
+  x.h = take ? h : x.h;
 }
 
 // lane `lane` of x takes the uniform order v
@@ -276,9 +269,7 @@ __device__ __forceinline__ void put(Chunk &x, const Chunk &v, int lane) {
   x.p = wl(x.p, v.p, lane);
   x.q = wl(x.q, v.q, lane);
   x.o = wl(x.o, v.o, lane);
-  x.t = wl(x.t, v.t, lane);
-  x.ts = wl(x.ts, v.ts, lane);
-  x.tns = wl(x.tns, v.tns, lane);
+  x.h = wl(x.h, v.h, lane);
 }
 
 // Slots (k, n) of a side move down by one (slot k < 128 is dropped); in the TAIL
@@ -334,9 +325,7 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
     S.c0.p = from_lane(S.c0.p, src);
     S.c0.q = from_lane(S.c0.q, src);
     S.c0.o = from_lane(S.c0.o, src);
-    S.c0.t = from_lane(S.c0.t, src);
-    S.c0.ts = from_lane(S.c0.ts, src);
-    S.c0.tns = from_lane(S.c0.tns, src);
+    S.c0.h = from_lane(S.c0.h, src);
     lds_wait();
     return;
   }
@@ -344,23 +333,17 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
   a.p = from_lane(S.c0.p, src);
   a.q = from_lane(S.c0.q, src);
   a.o = from_lane(S.c0.o, src);
-  a.t = from_lane(S.c0.t, src);
-  a.ts = from_lane(S.c0.ts, src);
-  a.tns = from_lane(S.c0.tns, src);
+  a.h = from_lane(S.c0.h, src);
   b.p = from_lane(S.c1.p, src);
   b.q = from_lane(S.c1.q, src);
   b.o = from_lane(S.c1.o, src);
-  b.t = from_lane(S.c1.t, src);
-  b.ts = from_lane(S.c1.ts, src);
-  b.tns = from_lane(S.c1.tns, src);
+  b.h = from_lane(S.c1.h, src);
   if (m < kWave) {
     const bool low = l + m < kWave;  // the source slot is in the same chunk
     S.c0.p = low ? a.p : b.p;
     S.c0.q = low ? a.q : b.q;
     S.c0.o = low ? a.o : b.o;
-    S.c0.t = low ? a.t : b.t;
-    S.c0.ts = low ? a.ts : b.ts;
-    S.c0.tns = low ? a.tns : b.tns;
+    S.c0.h = low ? a.h : b.h;
     S.c1 = b;
   } else {
     S.c0 = b;  // slot l takes slot 64 + (l + m - 64)
@@ -373,9 +356,9 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 // EXTRA: the launch collects agent fills or per-message L2 (else those checks are
 // compiled out).  LIMIT: a limit order, which more often than not rests untouched
 // (a layout hint only).
+// The aggressor is message j of the chunk v = (OID, TID, Ts, Tns) across the lanes.
 template <int OPP, bool TAIL, bool EXTRA, bool LIMIT>
-__device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, int q, int a_oid, int a_tid, int ts,
-                                     int tns) {
+__device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, int q, const int4 &v, int j) {
   Side &S = side<OPP>(bk);
   const Tail &tl = bk.tl[OPP];
   int n = st.n[OPP];
@@ -384,12 +367,14 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
   const int bp = rdlane(S.c0.p, 0);
   const bool apart = buyer ? bp > lim : bp < lim;  // the best standing price does not overlap
   if (LIMIT ? LOB_LIKELY(apart) : LOB_UNLIKELY(apart)) return q;
+  const int a_oid = rdlane(v.x, j), ts = rdlane(v.z, j), tns = rdlane(v.w, j);
   const int bq = rdlane(S.c0.q, 0);
   if (LOB_LIKELY(q <= bq)) {
     // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
     const int bo = rdlane(S.c0.o, 0);
     stage_one(st, sg, bp, q, bo, a_oid, ts, tns);
-    if (EXTRA && st.fills) fills_one(st, bp, q, bo, a_oid, ts, tns, rdlane(S.c0.t, 0), a_tid);
+    if (EXTRA && st.fills)
+      fills_one(st, bp, q, bo, a_oid, ts, tns, (rdlane(S.c0.h, 0) & 1) != 0, rdlane(v.y, j));
     if (q < bq) {
       S.c0.q = wl(S.c0.q, bq - q, 0);
     } else {
@@ -424,7 +409,7 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
       const int nfull = popc(mc & ballot(incl <= q));
       const int fill = takes ? min(qv, q - excl) : 0;
       stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
-      if constexpr (EXTRA) fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, F.t, a_tid);
+      if constexpr (EXTRA) fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, (F.h & 1) != 0, rdlane(v.y, j));
       F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
       const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
       q -= consumed;
@@ -443,8 +428,9 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
 
 // Add (Section 4.1, item 1) on side SD: the new order goes behind every order with
 // an equal or better price, i.e. at its price-time position.
+// hnd: the new order's handle.
 template <int SD, bool TAIL>
-__device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oid, int tid, int ts, int tns) {
+__device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oid, int hnd) {
   Side &S = side<SD>(bk);
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
@@ -463,9 +449,7 @@ __device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oi
   v.p = P;
   v.q = Q;
   v.o = oid;
-  v.t = tid;
-  v.ts = ts;
-  v.tns = tns;
+  v.h = hnd;
   if constexpr (TAIL) {
     if (pos == kSlots) {
       // behind every register order: into the tail.  The tail orders ahead of it
@@ -661,6 +645,15 @@ __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L,
   l2_side<TAIL>(bk.bid, bk.tl[1], st.n[1], L, o + L);
 }
 
+// Handle of the order added by message k (j of the chunk v): 2k, plus 1 when the
+// launch collects agent fills and the message carries the agent's trader id.
+template <bool EXTRA>
+__device__ __forceinline__ int handle(const State &st, int k, const int4 &v, int j) {
+  int h = k * 2;
+  if constexpr (EXTRA) h += (rdlane(v.y, j) == st.agent_tid) ? 1 : 0;
+  return h;
+}
+
 // One message (Section 4.2) given its case code: 1/2 limit sell/buy, 3/4 market
 // sell/buy, 5/6 cancel-or-delete on the ask/bid side, 0 not processed.  Limit:
 // match, then rest the remainder as one new order (item 1); market: match at
@@ -668,21 +661,21 @@ __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L,
 // the same operation (item 2).  One straight call sequence per case, so that no
 // flag derived from the case has to survive across branches.
 // Message j of the chunk held as u = (type, side, P, Q), v = (oid, tid, ts, tns)
-// across the lanes; each case reads only the fields it uses.
+// across the lanes, message k of the book's stream; each case reads only the
+// fields it uses.
 template <bool TAIL, bool EXTRA>
 __device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, const int4 &u, const int4 &v,
-                                            int j) {
+                                            int j, int k) {
   // tested in order of frequency: limit orders, cancels, market orders
   if (LOB_LIKELY((unsigned)(code - 1) < 2u)) {
-    const int P = rdlane(u.z, j), Q = rdlane(u.w, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j),
-              ts = rdlane(v.z, j), tns = rdlane(v.w, j);
+    const int P = rdlane(u.z, j), Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 0
     if (code == 1) {
-      const int rem = match<1, TAIL, EXTRA, true>(bk, st, sg, P, Q, oid, tid, ts, tns);
-      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
+      const int rem = match<1, TAIL, EXTRA, true>(bk, st, sg, P, Q, v, j);
+      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<EXTRA>(st, k, v, j));
     } else {
-      const int rem = match<0, TAIL, EXTRA, true>(bk, st, sg, P, Q, oid, tid, ts, tns);
-      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, oid, tid, ts, tns);
+      const int rem = match<0, TAIL, EXTRA, true>(bk, st, sg, P, Q, v, j);
+      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<EXTRA>(st, k, v, j));
     }
   } else if (code >= 5) {
     if (code == 5)
@@ -690,11 +683,10 @@ __device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int 
     else
       cancel<1, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
   } else if (code != 0) {
-    const int Q = rdlane(u.w, j), oid = rdlane(v.x, j), tid = rdlane(v.y, j), ts = rdlane(v.z, j),
-              tns = rdlane(v.w, j);
+    const int Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);
-    const int rem = code == 3 ? match<1, TAIL, EXTRA, false>(bk, st, sg, 0, Q, oid, tid, ts, tns)
-                              : match<0, TAIL, EXTRA, false>(bk, st, sg, INT_MAX, Q, oid, tid, ts, tns);
+    const int rem = code == 3 ? match<1, TAIL, EXTRA, false>(bk, st, sg, 0, Q, v, j)
+                              : match<0, TAIL, EXTRA, false>(bk, st, sg, INT_MAX, Q, v, j);
     if (rem > 0) st.market_discarded += (unsigned)rem;
   }
 }
@@ -756,7 +748,7 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
 #pragma nounroll
     for (int j = 0; j < cnt; ++j) {
       const int c = rdlane(code, j);
-      process_msg<TAIL, EXTRA>(bk, st, sg, c, u, v, j);
+      process_msg<TAIL, EXTRA>(bk, st, sg, c, u, v, j, (int)k0 + j);
       if constexpr (EXTRA) {
         if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
       }
@@ -764,26 +756,59 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
   }
 }
 
-__device__ __forceinline__ void load_chunk(Chunk &x, const int2 *base, int cap, int s, int n) {
+// Slot s (< n) of one side of the loaded book: its P, Q, OID and handle.
+template <bool EXTRA>
+__device__ __forceinline__ Chunk load_slot(const int2 *base, int cap, int s, int agent_tid) {
+  const int2 pq = base[s], ot = base[cap + s];
+  Chunk x;
+  x.p = pq.x;
+  x.q = pq.y;
+  x.o = ot.x;
+  x.h = (-1 - s) * 2 + ((EXTRA && ot.y == agent_tid) ? 1 : 0);
+  return x;
+}
+
+__device__ __forceinline__ void load_chunk(Chunk &x, const int2 *base, int cap, int s, int n, int agent_tid,
+                                           bool extra) {
   if (s < n) {
-    const int2 pq = base[s], ot = base[cap + s], tt = base[2 * cap + s];
-    x.p = pq.x;
-    x.q = pq.y;
-    x.o = ot.x;
-    x.t = ot.y;
-    x.ts = tt.x;
-    x.tns = tt.y;
+    x = extra ? load_slot<true>(base, cap, s, agent_tid) : load_slot<false>(base, cap, s, agent_tid);
   } else {
-    x.p = x.q = x.o = x.t = x.ts = x.tns = 0;
+    x.p = x.q = x.o = x.h = 0;
   }
 }
 
-__device__ __forceinline__ void store_chunk(const Chunk &x, int2 *base, int cap, int s, int n) {
-  if (s < n) {
-    base[s] = make_int2(x.p, x.q);
-    base[cap + s] = make_int2(x.o, x.t);
-    base[2 * cap + s] = make_int2(x.ts, x.tns);
+// Where the stream of the book being processed lives (for the handles' records).
+struct Streams {
+  const int32_t *msgs, *msgs2;
+  long long beg1, n1, beg2, total;
+};
+
+// Order x (one per lane) stored at slot s of one side of the written book `dst`;
+// its TID, Ts, Tns come through its handle from the stream or from the loaded
+// side `src` (the other buffer, not written by this launch).
+__device__ __forceinline__ void store_order(const Chunk &x, int2 *dst, const int2 *src, int cap, int s,
+                                            const Streams &m) {
+  long long idx = x.h >> 1;
+  int t, ts, tns;
+  if (idx >= 0) {
+    if (idx >= m.total) idx = m.total - 1;  // (cannot happen: a handle names a message of this stream)
+    const int32_t *rec = idx < m.n1 ? m.msgs + (m.beg1 + idx) * kMsgFields
+                                    : m.msgs2 + (m.beg2 + idx - m.n1) * kMsgFields;
+    const int4 r = reinterpret_cast<const int4 *>(rec)[1];  // (OID, TID, Ts, Tns)
+    t = r.y;
+    ts = r.z;
+    tns = r.w;
+  } else {
+    int os = (int)(-1 - idx);
+    if (os >= cap) os = cap - 1;  // (cannot happen: a loaded slot is below the capacity)
+    t = src[cap + os].y;
+    const int2 tt = src[2 * cap + os];
+    ts = tt.x;
+    tns = tt.y;
   }
+  dst[s] = make_int2(x.p, x.q);
+  dst[cap + s] = make_int2(x.o, t);
+  dst[2 * cap + s] = make_int2(ts, tns);
 }
 
 // TAIL form: tails of the two sides in LDS at `lds`, a.W entries each.
@@ -823,33 +848,6 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   st.fill_count = 0;
   st.agent_tid = a.agent_tid;
 
-  int2 *hb = a.books + uni64(h->book_off);
-  const int cap = st.cap;
-  Book bk;
-  load_chunk(bk.ask.c0, hb, cap, l, st.n[0]);
-  load_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0]);
-  load_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1]);
-  load_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1]);
-  if constexpr (TAIL) {
-    // slot s >= 128 of a side holding n orders is tail entry n - 1 - s
-    for (int sd = 0; sd < 2; ++sd) {
-      Tail &t = bk.tl[sd];
-      t.a = reinterpret_cast<int4 *>(lds + sd * 3 * a.W);  // 16-byte aligned: a.W int4 = 2 a.W int2
-      t.b = lds + sd * 3 * a.W + 2 * a.W;
-      const int n = st.n[sd];
-      const int2 *src = hb + (int64_t)sd * 3 * cap;
-      for (int s = kSlots + l; s < n; s += kWave) {
-        const int e = n - 1 - s;
-        const int2 pq = src[s], ot = src[cap + s];
-        t.a[e] = make_int4(pq.x, pq.y, ot.x, ot.y);
-        t.b[e] = src[2 * cap + s];
-      }
-    }
-  }
-  Stage sg;
-  sg.p = sg.q = sg.po = sg.ao = sg.ts = sg.tns = 0;
-  sg.k = 0;
-
   long long beg1 = 0, n1 = 0;
   if (a.msgs) {
     if (a.ranges) {
@@ -864,6 +862,36 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     }
   }
   const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
+  if (n1 + n2 >= (1LL << 30)) {  // handles hold message indices below 2^30
+    if (l == 0) h->flags |= kFlagBadLoad;
+    return;
+  }
+
+  // the loaded book, and the other buffer of this book, which receives the result
+  const long long off = uni64(h->book_off);
+  const long long off_out = off < a.books_half ? off + a.books_half : off - a.books_half;
+  const int2 *hb = a.books + off;
+  int2 *ob = a.books + off_out;
+  const int cap = st.cap;
+  Book bk;
+  load_chunk(bk.ask.c0, hb, cap, l, st.n[0], st.agent_tid, EXTRA);
+  load_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0], st.agent_tid, EXTRA);
+  load_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1], st.agent_tid, EXTRA);
+  load_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1], st.agent_tid, EXTRA);
+  if constexpr (TAIL) {
+    // slot s >= 128 of a side holding n orders is tail entry n - 1 - s
+    for (int sd = 0; sd < 2; ++sd) {
+      Tail &t = bk.tl[sd];
+      t.a = reinterpret_cast<int4 *>(lds + sd * 2 * a.W);  // a.W int4 per side
+      const int n = st.n[sd];
+      const int2 *src = hb + (int64_t)sd * 3 * cap;
+      for (int s = kSlots + l; s < n; s += kWave) tail_put(t, n - 1 - s, load_slot<EXTRA>(src, cap, s, st.agent_tid));
+    }
+  }
+  Stage sg;
+  sg.p = sg.q = sg.po = sg.ao = sg.ts = sg.tns = 0;
+  sg.k = 0;
+
   if (a.prio_len > 0 && n1 >= a.prio_len) __builtin_amdgcn_s_setprio(3);
   // per-message L2 rows of source 1: contiguous by message index, or l2_stride
   // int32 apart per listed book
@@ -873,22 +901,22 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   flush(st, sg);
   if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
-  store_chunk(bk.ask.c0, hb, cap, l, st.n[0]);
-  store_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0]);
-  store_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1]);
-  store_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1]);
-  if constexpr (TAIL) {
-    for (int sd = 0; sd < 2; ++sd) {
-      const Tail &t = bk.tl[sd];
-      const int n = st.n[sd];
-      int2 *dst = hb + (int64_t)sd * 3 * cap;
-      for (int s = kSlots + l; s < n; s += kWave) {
-        const int e = n - 1 - s;
-        const int4 v = t.a[e];
-        dst[s] = make_int2(v.x, v.y);
-        dst[cap + s] = make_int2(v.z, v.w);
-        dst[2 * cap + s] = t.b[e];
-      }
+  Streams ms;
+  ms.msgs = a.msgs;
+  ms.msgs2 = a.msgs2;
+  ms.beg1 = beg1;
+  ms.n1 = n1;
+  ms.beg2 = (long long)i * a.w2;
+  ms.total = n1 + n2;
+  for (int sd = 0; sd < 2; ++sd) {
+    const Side &S = sd == 0 ? bk.ask : bk.bid;
+    const int n = st.n[sd];
+    const int2 *src = hb + (int64_t)sd * 3 * cap;
+    int2 *dst = ob + (int64_t)sd * 3 * cap;
+    if (l < n) store_order(S.c0, dst, src, cap, l, ms);
+    if (kWave + l < n) store_order(S.c1, dst, src, cap, kWave + l, ms);
+    if constexpr (TAIL) {
+      for (int s = kSlots + l; s < n; s += kWave) store_order(tail_get(bk.tl[sd], n - 1 - s), dst, src, cap, s, ms);
     }
   }
   if (st.fills) {
@@ -896,6 +924,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     if (l == 0 && a.fill_counts) a.fill_counts[row] = st.fill_count;
   }
   if (l == 0) {
+    h->book_off = off_out;
     h->n[0] = st.n[0];
     h->n[1] = st.n[1];
     h->flags = st.flags;
@@ -940,7 +969,7 @@ __global__ void k_selftest_shift(int32_t *out) {
 int small_book_slots() { return kSlots; }
 
 // tail = false: books of capacity <= 128; tail = true: a.W tail entries per side in
-// LDS (a.lds_int2_per_wave = 6 * a.W per wave)
+// LDS (a.lds_int2_per_wave = 4 * a.W per wave)
 hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int threads = a.bpb * kWave;
   const int grid = (a.n + a.bpb - 1) / a.bpb;
