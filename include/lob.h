@@ -84,8 +84,10 @@ typedef int32_t lob_status;
 #define LOB_BOOK_TRADE_FULL 4   /* trades were dropped: the book's trade log full */
 #define LOB_BOOK_FILLS_FULL 8   /* agent fills were dropped: the fills buffer full */
 #define LOB_BOOK_BAD_LOAD 16    /* lob_write_book rows out of priority order or past
-                                   the capacity, or lob_seed_l2 given a snapshot
-                                   that is not a book                             */
+                                   the capacity, lob_seed_l2 given a snapshot that
+                                   is not a book, or a call of the register kernel
+                                   with 2^30 or more messages for one book (that
+                                   book is left untouched)                        */
 
 typedef struct {
   int32_t n_books;                       /* books in the context, >= 1             */

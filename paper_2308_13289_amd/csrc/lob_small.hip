@@ -132,6 +132,22 @@ __device__ __forceinline__ void pick(Chunk &x, bool c, const Chunk &v) {
   x.h = c ? v.h : x.h;
 }
 
+// Wave-uniform state of the book being processed.  The counters are this call's
+// increments, added to the header's at the end; counts of trades, log records and
+// missed cancels fit 32 bits because a call gives a book fewer than 2^30 messages.
+struct RState {
+  int n[2];
+  int cap, flags;
+  int trades, misses;
+  long long limit_qty, market_qty, traded_qty, cancelled_qty, market_discarded, rejected_qty;
+  int last_ts, last_tns, seen;
+  int32_t *log;  // the book's next free log record, or nullptr
+  int log_room;  // records that still fit in the log
+  int logged;    // records stored by this call
+  int32_t *fills;
+  int fill_cap, fill_count, agent_tid;
+};
+
 // Pending trade records, one per lane; k of them (uniform) are pending.
 struct Stage {
   int p, q, po, ao, ts, tns;
@@ -146,28 +162,29 @@ __device__ __forceinline__ long long wave_sum(int v) {
 }
 
 // The pending trades are counted (trades and traded quantity) and stored.
-__device__ __forceinline__ void flush(State &st, Stage &sg) {
+__device__ __forceinline__ void flush(RState &st, Stage &sg) {
   if (sg.k == 0) return;
-  st.n_trades += sg.k;
+  st.trades += sg.k;
   st.traded_qty += wave_sum(lane_id() < sg.k ? sg.q : 0);
   if (st.log) {
-    const long long room = st.log_cap - st.log_count;
-    const int stored = room < sg.k ? (room > 0 ? (int)room : 0) : sg.k;
+    const int stored = st.log_room < sg.k ? st.log_room : sg.k;
     const int l = lane_id();
     if (l < stored) {
-      int2 *r = reinterpret_cast<int2 *>(st.log + (st.log_count + l) * kTradeFields);
+      int2 *r = reinterpret_cast<int2 *>(st.log + l * kTradeFields);
       r[0] = make_int2(sg.p, sg.q);
       r[1] = make_int2(sg.po, sg.ao);
       r[2] = make_int2(sg.ts, sg.tns);
     }
     if (stored < sg.k) st.flags |= kFlagTradeFull;
-    st.log_count += stored;
+    st.log += stored * kTradeFields;
+    st.log_room -= stored;
+    st.logged += stored;
   }
   sg.k = 0;
 }
 
 // One trade from uniform values.
-__device__ __forceinline__ void stage_one(State &st, Stage &sg, int P, int fill, int po, int ao, int ts, int tns) {
+__device__ __forceinline__ void stage_one(RState &st, Stage &sg, int P, int fill, int po, int ao, int ts, int tns) {
   sg.p = wl(sg.p, P, sg.k);
   sg.q = wl(sg.q, fill, sg.k);
   sg.po = wl(sg.po, po, sg.k);
@@ -179,7 +196,7 @@ __device__ __forceinline__ void stage_one(State &st, Stage &sg, int P, int fill,
 
 // ntr trades held by lanes [0, ntr) (P, fill, passive id per lane; the aggressor
 // fields are uniform): rotate them behind the pending ones.
-__device__ __forceinline__ void stage_many(State &st, Stage &sg, int ntr, int P, int fill, int po, int ao, int ts,
+__device__ __forceinline__ void stage_many(RState &st, Stage &sg, int ntr, int P, int fill, int po, int ao, int ts,
                                            int tns) {
   const int l = lane_id();
   const int src = (l - sg.k) & 63;
@@ -208,7 +225,7 @@ __device__ __forceinline__ void stage_many(State &st, Stage &sg, int ntr, int P,
 }
 
 // Agent fills (step form): trades where either side carries the agent's trader id.
-__device__ __forceinline__ void fills_one(State &st, int P, int fill, int po, int ao, int ts, int tns, bool pag,
+__device__ __forceinline__ void fills_one(RState &st, int P, int fill, int po, int ao, int ts, int tns, bool pag,
                                           int atid) {
   if (!st.fills || (!pag && atid != st.agent_tid)) return;
   if (st.fill_count < st.fill_cap && lane_id() == 0) {
@@ -220,7 +237,7 @@ __device__ __forceinline__ void fills_one(State &st, int P, int fill, int po, in
   st.fill_count++;
 }
 
-__device__ __forceinline__ void fills_many(State &st, bool takes, int P, int fill, int po, int ao, int ts, int tns,
+__device__ __forceinline__ void fills_many(RState &st, bool takes, int P, int fill, int po, int ao, int ts, int tns,
                                            bool pag, int atid) {
   if (!st.fills) return;
   const bool ag = takes & (pag | (atid == st.agent_tid));
@@ -358,7 +375,7 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 // (a layout hint only).
 // The aggressor is message j of the chunk v = (OID, TID, Ts, Tns) across the lanes.
 template <int OPP, bool TAIL, bool EXTRA, bool LIMIT>
-__device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, int q, const int4 &v, int j) {
+__device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, int q, const int4 &v, int j) {
   Side &S = side<OPP>(bk);
   const Tail &tl = bk.tl[OPP];
   int n = st.n[OPP];
@@ -430,7 +447,7 @@ __device__ __forceinline__ int match(Book &bk, State &st, Stage &sg, int lim, in
 // an equal or better price, i.e. at its price-time position.
 // hnd: the new order's handle.
 template <int SD, bool TAIL>
-__device__ __forceinline__ void insert(Book &bk, State &st, int P, int Q, int oid, int hnd) {
+__device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int oid, int hnd) {
   Side &S = side<SD>(bk);
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
@@ -512,7 +529,7 @@ __device__ __forceinline__ int tail_find(int T, Pred pred) {
 
 // Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders) on side SD.
 template <int SD, bool TAIL>
-__device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, int price) {
+__device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, int price) {
   Side &S = side<SD>(bk);
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
@@ -555,7 +572,7 @@ __device__ __forceinline__ void cancel(Book &bk, State &st, int oid, int qty, in
     }
   }
   if (k < 0 && t < 0) {
-    st.cancel_miss++;
+    st.misses++;
     return;
   }
   if constexpr (TAIL) {
@@ -639,7 +656,7 @@ __device__ __forceinline__ void l2_side(const Side &S, const Tail &tl, int n, in
 }
 
 template <bool TAIL>
-__device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L, int32_t *row) {
+__device__ __forceinline__ void write_l2(const Book &bk, const RState &st, int L, int32_t *row) {
   int2 *o = reinterpret_cast<int2 *>(row);
   l2_side<TAIL>(bk.ask, bk.tl[0], st.n[0], L, o);
   l2_side<TAIL>(bk.bid, bk.tl[1], st.n[1], L, o + L);
@@ -648,7 +665,7 @@ __device__ __forceinline__ void write_l2(const Book &bk, const State &st, int L,
 // Handle of the order added by message k (j of the chunk v): 2k, plus 1 when the
 // launch collects agent fills and the message carries the agent's trader id.
 template <bool EXTRA>
-__device__ __forceinline__ int handle(const State &st, int k, const int4 &v, int j) {
+__device__ __forceinline__ int handle(const RState &st, int k, const int4 &v, int j) {
   int h = k * 2;
   if constexpr (EXTRA) h += (rdlane(v.y, j) == st.agent_tid) ? 1 : 0;
   return h;
@@ -664,7 +681,7 @@ __device__ __forceinline__ int handle(const State &st, int k, const int4 &v, int
 // across the lanes, message k of the book's stream; each case reads only the
 // fields it uses.
 template <bool TAIL, bool EXTRA>
-__device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int code, const int4 &u, const int4 &v,
+__device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int code, const int4 &u, const int4 &v,
                                             int j, int k) {
   // tested in order of frequency: limit orders, cancels, market orders
   if (LOB_LIKELY((unsigned)(code - 1) < 2u)) {
@@ -694,7 +711,7 @@ __device__ __forceinline__ void process_msg(Book &bk, State &st, Stage &sg, int 
 // The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
 // form's agent orders) msgs2[beg2, beg2 + n2), in 64-message chunks.
 template <bool TAIL, bool EXTRA>
-__device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, const ProcArgs &a, long long beg1,
+__device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, const ProcArgs &a, long long beg1,
                                             long long n1, long long beg2, long long n2, int32_t *l2_rows) {
   const int l = lane_id();
   const long long total = n1 + n2;
@@ -742,7 +759,6 @@ __device__ __forceinline__ void process_all(Book &bk, State &st, Stage &sg, cons
       st.limit_qty += wave_sum(((code == 1) | (code == 2)) ? qpos : 0);
       st.market_qty += wave_sum(((code == 3) | (code == 4)) ? qpos : 0);
     }
-    st.n_msgs += cnt;
     // messages of this chunk that come from source 1 (they get per-message L2 rows)
     const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
 #pragma nounroll
@@ -818,7 +834,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   const int book = a.book_ids ? uni(a.book_ids[i]) : i;
   if (book < 0 || book >= a.n_total) return;
   BookHdr *h = a.hdr + book;
-  State st;
+  RState st;
   st.n[0] = uni(h->n[0]);
   st.n[1] = uni(h->n[1]);
   st.cap = uni(h->cap);
@@ -827,21 +843,17 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     return;
   }
   st.flags = uni(h->flags);
-  st.n_msgs = uni64(h->n_msgs);
-  st.n_trades = uni64(h->n_trades);
-  st.limit_qty = uni64(h->limit_qty);
-  st.market_qty = uni64(h->market_qty);
-  st.traded_qty = uni64(h->traded_qty);
-  st.cancelled_qty = uni64(h->cancelled_qty);
-  st.market_discarded = uni64(h->market_discarded);
-  st.rejected_qty = uni64(h->rejected_qty);
-  st.cancel_miss = uni64(h->cancel_miss);
+  st.trades = st.misses = 0;
+  st.limit_qty = st.market_qty = st.traded_qty = st.cancelled_qty = st.market_discarded = st.rejected_qty = 0;
   st.last_ts = uni(h->last_ts);
   st.last_tns = uni(h->last_tns);
   st.seen = uni(h->seen_time);
-  st.log_cap = uni64(h->log_cap);
-  st.log_count = uni64(h->log_count);
-  st.log = a.log ? a.log + uni64(h->log_off) * kTradeFields : nullptr;
+  {
+    const long long count = uni64(h->log_count), room = uni64(h->log_cap) - count;
+    st.log = a.log ? a.log + (uni64(h->log_off) + count) * kTradeFields : nullptr;
+    st.log_room = room < 0 ? 0 : (room > INT_MAX ? INT_MAX : (int)room);
+    st.logged = 0;
+  }
   const int row = a.out_rows ? uni(a.out_rows[i]) : i;  // output row of this book
   st.fills = a.fills ? a.fills + (int64_t)row * a.fill_cap * kTradeFields : nullptr;
   st.fill_cap = a.fill_cap;
@@ -928,19 +940,19 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     h->n[0] = st.n[0];
     h->n[1] = st.n[1];
     h->flags = st.flags;
-    h->n_msgs = st.n_msgs;
-    h->n_trades = st.n_trades;
-    h->limit_qty = st.limit_qty;
-    h->market_qty = st.market_qty;
-    h->traded_qty = st.traded_qty;
-    h->cancelled_qty = st.cancelled_qty;
-    h->market_discarded = st.market_discarded;
-    h->rejected_qty = st.rejected_qty;
-    h->cancel_miss = st.cancel_miss;
+    h->n_msgs += n1 + n2;
+    h->n_trades += st.trades;
+    h->limit_qty += st.limit_qty;
+    h->market_qty += st.market_qty;
+    h->traded_qty += st.traded_qty;
+    h->cancelled_qty += st.cancelled_qty;
+    h->market_discarded += st.market_discarded;
+    h->rejected_qty += st.rejected_qty;
+    h->cancel_miss += st.misses;
     h->last_ts = st.last_ts;
     h->last_tns = st.last_tns;
     h->seen_time = st.seen;
-    h->log_count = st.log_count;
+    h->log_count += st.logged;
   }
 }
 

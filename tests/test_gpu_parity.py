@@ -17,7 +17,7 @@ if not gpu_available():  # pragma: no cover - collected on CPU hosts too
     pytest.skip("no GPU", allow_module_level=True)
 
 from golden_cases import all_cases  # noqa: E402
-from gpu_helpers import assert_same, new_context, run_gpu, run_oracle, to_dev  # noqa: E402
+from gpu_helpers import COUNTERS, assert_same, new_context, run_gpu, run_oracle, to_dev  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from paper_2308_13289_amd import lob  # noqa: E402
 from paper_2308_13289_amd import workload as W  # noqa: E402
@@ -212,6 +212,43 @@ def test_split_calls_equal_one_call():
     g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_PER_MESSAGE, calls=3)
     o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_PER_MESSAGE)
     assert_same(g, o, "3 calls")
+
+
+@pytest.mark.parametrize("cap", [100, 300])
+def test_residency_switch_between_calls(cap):
+    """Consecutive calls on one context alternate the register kernel (which writes
+    each book to its second buffer), the LDS kernel and the unsorted layout (which
+    work in place), with a book read in between: the result equals one oracle run."""
+    w = W.uniform(24, 1800, cap=cap, tag=95)
+    lens = np.diff(w.offs)
+    ctx = new_context(w.caps, 10, lens)
+    plans = [RESIDENCY["regs"], RESIDENCY["lds"], RESIDENCY["regs"], RESIDENCY["unsorted"], RESIDENCY["regs"],
+             RESIDENCY["regs"]]
+    calls = len(plans)
+    l2 = torch.zeros((w.n_books, 2, 10, 2), dtype=torch.int32, device="cuda:0")
+    for c, plan in enumerate(plans):
+        ctx.set_plan(**plan)
+        lo = w.offs[:-1] + (lens * c) // calls
+        hi = w.offs[:-1] + (lens * (c + 1)) // calls
+        idx = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+        sub_offs = np.concatenate([[0], np.cumsum(hi - lo)]).astype(np.int64)
+        ctx.process(to_dev(w.msgs[idx]), to_dev(sub_offs), l2_mode=lob.L2_FINAL, l2_out=l2)
+        if c == 2:
+            part = O.run(w.caps, w.msgs[np.concatenate([np.arange(a, b) for a, b in zip(w.offs[:-1], hi)])],
+                         np.concatenate([[0], np.cumsum(hi - w.offs[:-1])]).astype(np.int64), dumps=True,
+                         dump_cap=cap)
+            np.testing.assert_array_equal(ctx.read_book(cap).cpu().numpy(), part["dumps"], err_msg="after 3 calls")
+    torch.cuda.synchronize()
+    o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
+    st = ctx.read_status()
+    total = int(st["log_records"].sum())
+    rec, _, toffs = ctx.read_trades(max(total, 1))
+    np.testing.assert_array_equal(toffs.cpu().numpy(), o["trade_offs"])
+    np.testing.assert_array_equal(rec[:total].cpu().numpy(), o["trades"][:, :6])
+    np.testing.assert_array_equal(ctx.read_book(cap).cpu().numpy(), o["dumps"])
+    np.testing.assert_array_equal(l2.cpu().numpy(), o["l2"])
+    for k in COUNTERS:
+        np.testing.assert_array_equal(st[k], o["stats"][k], err_msg=k)
 
 
 def test_checkpoint_resume():
