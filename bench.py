@@ -460,6 +460,20 @@ def bench_layout(args, reps=3):
     return out
 
 
+def bench_occupancy(args, reps=3):
+    """The C1 book shape (capacity 100, 100 initial + 10,000 flow messages) at 1, 2,
+    4, 8 and 16 books per SIMD: the serial latency of one book against the
+    throughput more waves in flight reach (default plan)."""
+    out = []
+    for n in (1024, 2048, 4096, 8192, 16384):
+        w = W.uniform(n, 10_000, tag=W.TAGS["c1"], threads=host_cores(), name=f"uniform{n}x10000c100")
+        r = _time_plan(w, {"registers": 1}, reps)
+        out.append({"books": n, "kernel_ms": r["kernel_ms"], "msgs_per_s": r["msgs_per_s"],
+                    "ns_per_msg_per_book": r["kernel_ms"] * 1e6 / (w.n_msgs / n), "ok": r["ok"]})
+        del w
+    return {"occupancy": out}
+
+
 # the paper's own timings (RTX 2080 Ti, JAX; Tables 1-4), quoted as context
 PAPER_MS = {
     "single_book": {10: {"add": 0.115, "cancel": 0.081, "match": 0.184},
@@ -562,7 +576,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout"])
+                    choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout", "occupancy"])
     ap.add_argument("--tune-trials", type=int, default=16)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
@@ -593,6 +607,9 @@ def main():
         return
     if args.workload == "layout":
         print(json.dumps(bench_layout(args)), flush=True)
+        return
+    if args.workload == "occupancy":
+        print(json.dumps(bench_occupancy(args)), flush=True)
         return
     t0 = time.perf_counter()
     if args.workload in ("c1", "all"):
