@@ -148,9 +148,12 @@ struct RState {
   int fill_cap, fill_count, agent_tid;
 };
 
-// Pending trade records, one per lane; k of them (uniform) are pending.
+// Pending trade records, one per lane; k of them (uniform) are pending.  A record
+// keeps the standing order's price, the fill and the standing id; the aggressor's
+// id and time are those of message j of the current chunk, fetched when the
+// records are stored, which happens at the latest when the chunk ends.
 struct Stage {
-  int p, q, po, ao, ts, tns;
+  int p, q, po, j;
   int k;
 };
 
@@ -161,19 +164,21 @@ __device__ __forceinline__ long long wave_sum(int v) {
   return (long long)rdlane(lo, 63) + ((long long)rdlane(hi, 63) << 16);
 }
 
-// The pending trades are counted (trades and traded quantity) and stored.
-__device__ __forceinline__ void flush(RState &st, Stage &sg) {
+// The pending trades are counted (trades and traded quantity) and stored; v holds
+// (OID, TID, Ts, Tns) of the chunk's messages across the lanes.
+__device__ __forceinline__ void flush(RState &st, Stage &sg, const int4 &v) {
   if (sg.k == 0) return;
   st.trades += sg.k;
   st.traded_qty += wave_sum(lane_id() < sg.k ? sg.q : 0);
   if (st.log) {
     const int stored = st.log_room < sg.k ? st.log_room : sg.k;
     const int l = lane_id();
+    const int ao = from_lane(v.x, sg.j), ts = from_lane(v.z, sg.j), tns = from_lane(v.w, sg.j);
     if (l < stored) {
       int2 *r = reinterpret_cast<int2 *>(st.log + l * kTradeFields);
       r[0] = make_int2(sg.p, sg.q);
-      r[1] = make_int2(sg.po, sg.ao);
-      r[2] = make_int2(sg.ts, sg.tns);
+      r[1] = make_int2(sg.po, ao);
+      r[2] = make_int2(ts, tns);
     }
     if (stored < sg.k) st.flags |= kFlagTradeFull;
     st.log += stored * kTradeFields;
@@ -183,21 +188,19 @@ __device__ __forceinline__ void flush(RState &st, Stage &sg) {
   sg.k = 0;
 }
 
-// One trade from uniform values.
-__device__ __forceinline__ void stage_one(RState &st, Stage &sg, int P, int fill, int po, int ao, int ts, int tns) {
+// One trade from uniform values; the aggressor is message j of the chunk v.
+__device__ __forceinline__ void stage_one(RState &st, Stage &sg, int P, int fill, int po, int j, const int4 &v) {
   sg.p = wl(sg.p, P, sg.k);
   sg.q = wl(sg.q, fill, sg.k);
   sg.po = wl(sg.po, po, sg.k);
-  sg.ao = wl(sg.ao, ao, sg.k);
-  sg.ts = wl(sg.ts, ts, sg.k);
-  sg.tns = wl(sg.tns, tns, sg.k);
-  if (LOB_UNLIKELY(++sg.k == kWave)) flush(st, sg);
+  sg.j = wl(sg.j, j, sg.k);
+  if (LOB_UNLIKELY(++sg.k == kWave)) flush(st, sg, v);
 }
 
-// ntr trades held by lanes [0, ntr) (P, fill, passive id per lane; the aggressor
-// fields are uniform): rotate them behind the pending ones.
-__device__ __forceinline__ void stage_many(RState &st, Stage &sg, int ntr, int P, int fill, int po, int ao, int ts,
-                                           int tns) {
+// ntr trades held by lanes [0, ntr) (P, fill, standing id per lane; the aggressor
+// is message j of the chunk v): rotate them behind the pending ones.
+__device__ __forceinline__ void stage_many(RState &st, Stage &sg, int ntr, int P, int fill, int po, int j,
+                                           const int4 &v) {
   const int l = lane_id();
   const int src = (l - sg.k) & 63;
   const int rp = from_lane(P, src), rq = from_lane(fill, src), ro = from_lane(po, src);
@@ -205,19 +208,15 @@ __device__ __forceinline__ void stage_many(RState &st, Stage &sg, int ntr, int P
   sg.p = mine ? rp : sg.p;
   sg.q = mine ? rq : sg.q;
   sg.po = mine ? ro : sg.po;
-  sg.ao = mine ? ao : sg.ao;
-  sg.ts = mine ? ts : sg.ts;
-  sg.tns = mine ? tns : sg.tns;
+  sg.j = mine ? j : sg.j;
   const int end = sg.k + ntr;
   if (end >= kWave) {
     sg.k = kWave;
-    flush(st, sg);
+    flush(st, sg, v);
     sg.p = rp;
     sg.q = rq;
     sg.po = ro;
-    sg.ao = ao;
-    sg.ts = ts;
-    sg.tns = tns;
+    sg.j = j;
     sg.k = end - kWave;
   } else {
     sg.k = end;
@@ -384,14 +383,14 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
   const int bp = rdlane(S.c0.p, 0);
   const bool apart = buyer ? bp > lim : bp < lim;  // the best standing price does not overlap
   if (LIMIT ? LOB_LIKELY(apart) : LOB_UNLIKELY(apart)) return q;
-  const int a_oid = rdlane(v.x, j), ts = rdlane(v.z, j), tns = rdlane(v.w, j);
   const int bq = rdlane(S.c0.q, 0);
   if (LOB_LIKELY(q <= bq)) {
     // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
     const int bo = rdlane(S.c0.o, 0);
-    stage_one(st, sg, bp, q, bo, a_oid, ts, tns);
+    stage_one(st, sg, bp, q, bo, j, v);
     if (EXTRA && st.fills)
-      fills_one(st, bp, q, bo, a_oid, ts, tns, (rdlane(S.c0.h, 0) & 1) != 0, rdlane(v.y, j));
+      fills_one(st, bp, q, bo, rdlane(v.x, j), rdlane(v.z, j), rdlane(v.w, j), (rdlane(S.c0.h, 0) & 1) != 0,
+                rdlane(v.y, j));
     if (q < bq) {
       S.c0.q = wl(S.c0.q, bq - q, 0);
     } else {
@@ -425,8 +424,10 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
       const bool full = cross & (incl <= q);
       const int nfull = popc(mc & ballot(incl <= q));
       const int fill = takes ? min(qv, q - excl) : 0;
-      stage_many(st, sg, ntr, F.p, fill, F.o, a_oid, ts, tns);
-      if constexpr (EXTRA) fills_many(st, takes, F.p, fill, F.o, a_oid, ts, tns, (F.h & 1) != 0, rdlane(v.y, j));
+      stage_many(st, sg, ntr, F.p, fill, F.o, j, v);
+      if constexpr (EXTRA)
+        fills_many(st, takes, F.p, fill, F.o, rdlane(v.x, j), rdlane(v.z, j), rdlane(v.w, j), (F.h & 1) != 0,
+                   rdlane(v.y, j));
       F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
       const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
       q -= consumed;
@@ -769,6 +770,7 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
         if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
       }
     }
+    flush(st, sg, v);  // the staged records name messages of this chunk
   }
 }
 
@@ -901,7 +903,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     }
   }
   Stage sg;
-  sg.p = sg.q = sg.po = sg.ao = sg.ts = sg.tns = 0;
+  sg.p = sg.q = sg.po = sg.j = 0;
   sg.k = 0;
 
   if (a.prio_len > 0 && n1 >= a.prio_len) __builtin_amdgcn_s_setprio(3);
@@ -910,7 +912,6 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
                      : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
   process_all<TAIL, EXTRA>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
-  flush(st, sg);
   if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
   Streams ms;
