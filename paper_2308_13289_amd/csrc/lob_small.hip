@@ -460,9 +460,11 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
   }
   const int nr = n < kSlots ? n : kSlots;
   // the orders ahead (price equal or better) form a prefix, so chunk 1 holds some
-  // only when chunk 0 is all ahead: both counts add up without a test
-  const int pos = popc(ballot(l < nr) & ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P)) +
-                  popc(ballot(l + kWave < nr) & ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P));
+  // only when chunk 0 is all ahead: both counts add up without a test (without a
+  // tail chunk 1 is rarely in use and is skipped while it is empty)
+  int pos = popc(ballot(l < nr) & ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P));
+  if (TAIL || LOB_UNLIKELY(nr > kWave))
+    pos += popc(ballot(l + kWave < nr) & ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P));
   Chunk v;
   v.p = P;
   v.q = Q;
@@ -672,8 +674,8 @@ __device__ __forceinline__ int handle(const RState &st, int k, const int4 &v, in
   return h;
 }
 
-// One message (Section 4.2) given its case code: 1/2 limit sell/buy, 3/4 market
-// sell/buy, 5/6 cancel-or-delete on the ask/bid side, 0 not processed.  Limit:
+// One message (Section 4.2) given its case code: 0/1 limit sell/buy, 2/3
+// cancel-or-delete on the ask/bid side, 4/5 market sell/buy, 7 not processed.  Limit:
 // match, then rest the remainder as one new order (item 1); market: match at
 // price 0 (sell) / max_int (buy), drop the rest (item 3); cancel and delete are
 // the same operation (item 2).  One straight call sequence per case, so that no
@@ -685,25 +687,25 @@ template <bool TAIL, bool EXTRA>
 __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int code, const int4 &u, const int4 &v,
                                             int j, int k) {
   // tested in order of frequency: limit orders, cancels, market orders
-  if (LOB_LIKELY((unsigned)(code - 1) < 2u)) {
+  if (LOB_LIKELY(code < 2)) {
     const int P = rdlane(u.z, j), Q = rdlane(u.w, j);
-    __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 0
-    if (code == 1) {
+    __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 7
+    if (code == 0) {
       const int rem = match<1, TAIL, EXTRA, true>(bk, st, sg, P, Q, v, j);
       if (rem > 0) insert<0, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<EXTRA>(st, k, v, j));
     } else {
       const int rem = match<0, TAIL, EXTRA, true>(bk, st, sg, P, Q, v, j);
       if (rem > 0) insert<1, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<EXTRA>(st, k, v, j));
     }
-  } else if (code >= 5) {
-    if (code == 5)
+  } else if (code < 4) {
+    if (code == 2)
       cancel<0, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
     else
       cancel<1, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
-  } else if (code != 0) {
+  } else if (code < 6) {
     const int Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);
-    const int rem = code == 3 ? match<1, TAIL, EXTRA, false>(bk, st, sg, 0, Q, v, j)
+    const int rem = code == 4 ? match<1, TAIL, EXTRA, false>(bk, st, sg, 0, Q, v, j)
                               : match<0, TAIL, EXTRA, false>(bk, st, sg, INT_MAX, Q, v, j);
     if (rem > 0) st.market_discarded += (unsigned)rem;
   }
@@ -737,9 +739,9 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
     if (k0 + kWave < total) fetch(k0 + kWave, un, vn);
     const int T = u.x, S = u.y;
     const bool ok = (l < cnt) & (T >= 1) & (T <= 4) & ((S == 1) | (S == -1));
-    // code 0 also for Q <= 0: such a cancel removes nothing and such a limit or
+    // code 7 also for Q <= 0: such a cancel removes nothing and such a limit or
     // market order neither trades nor rests; only the counts and the time check see it
-    const int code = !(ok & (u.w > 0)) ? 0 : (T == 1 ? 1 : T == 4 ? 3 : 5) + (S == 1 ? 1 : 0);
+    const int code = !(ok & (u.w > 0)) ? 7 : (T == 1 ? 0 : T == 4 ? 4 : 2) + (S == 1 ? 1 : 0);
     const uint64_t vmask = ballot(ok);
     if (vmask) {
       // times of valid messages must not decrease: compare with the previous valid
@@ -757,8 +759,8 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
       st.seen = 1;
       // submitted quantity of limit and market orders (Q > 0 only)
       const int qpos = u.w > 0 ? u.w : 0;
-      st.limit_qty += wave_sum(((code == 1) | (code == 2)) ? qpos : 0);
-      st.market_qty += wave_sum(((code == 3) | (code == 4)) ? qpos : 0);
+      st.limit_qty += wave_sum(code < 2 ? qpos : 0);
+      st.market_qty += wave_sum((code >> 1) == 2 ? qpos : 0);
     }
     // messages of this chunk that come from source 1 (they get per-message L2 rows)
     const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
