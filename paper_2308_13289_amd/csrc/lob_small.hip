@@ -293,7 +293,7 @@ __device__ __forceinline__ void put(Chunk &x, const Chunk &v, int lane) {
 template <bool TAIL>
 __device__ __forceinline__ void remove_at(Side &S, const Tail &tl, int k, int n) {
   const int l = lane_id();
-  if (n > kWave) {
+  if (TAIL ? LOB_LIKELY(n > kWave) : LOB_UNLIKELY(n > kWave)) {
     const Chunk in = edge(S.c1, 0);  // slot 64 moves to slot 63
     shift_dn(S.c1, l + kWave >= k);
     if (k < kWave) {
@@ -471,7 +471,7 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
   v.o = oid;
   v.h = hnd;
   if constexpr (TAIL) {
-    if (pos == kSlots) {
+    if (LOB_UNLIKELY(pos == kSlots)) {
       // behind every register order: into the tail.  The tail orders ahead of it
       // (equal or better price) are the entries [T - c, T); they move up by one and
       // the new order takes entry T - c.
@@ -502,14 +502,14 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
     }
   }
   // (without a tail a side rarely holds 64 orders or more: chunk 1 work is laid out
-  // of line)
-  if (TAIL ? (nr >= kWave) : LOB_UNLIKELY(nr >= kWave)) {
+  // of line; with one it is the common case)
+  if (TAIL ? LOB_LIKELY(nr >= kWave) : LOB_UNLIKELY(nr >= kWave)) {
     // chunk 1 changes: slot 63 moves into slot 64, or the new order lands there
     const Chunk in = edge(S.c0, 63);
     shift_up(S.c1, l + kWave > pos);
     if (pos < kWave) put(S.c1, in, 0);
   }
-  if (TAIL ? (pos < kWave) : LOB_LIKELY(pos < kWave)) {
+  if (LOB_LIKELY(pos < kWave)) {
     shift_up(S.c0, l > pos);
     put(S.c0, v, pos);
   } else {
