@@ -41,6 +41,14 @@ constexpr int kSlots = 2 * kWave;  // orders per side the kernel holds
 #define LOB_LIKELY(x) __builtin_expect(!!(x), 1)
 #define LOB_UNLIKELY(x) __builtin_expect(!!(x), 0)
 
+// Lane masks of one signed compare each (a < b, a <= b, a >= b, a == b): a single
+// v_cmp whose result is the mask, which the compiler cannot turn into a 0/1
+// value carried across a branch and compared again.
+__device__ __forceinline__ uint64_t lt_mask(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 40); }
+__device__ __forceinline__ uint64_t le_mask(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 41); }
+__device__ __forceinline__ uint64_t ge_mask(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 39); }
+__device__ __forceinline__ uint64_t eq_mask(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 32); }
+
 // Wait for the wave's outstanding LDS operations (lgkmcnt 0; vmcnt, expcnt left at
 // their maxima), so that results of a ds_bpermute are in place before the next
 // message instead of being waited for at every later use.
@@ -184,6 +192,7 @@ __device__ __forceinline__ void flush(RState &st, Stage &sg, const int4 &v) {
     st.log += stored * kTradeFields;
     st.log_room -= stored;
     st.logged += stored;
+    lds_wait();  // the permutes are complete on every path out
   }
   sg.k = 0;
 }
@@ -459,12 +468,27 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
     return;
   }
   const int nr = n < kSlots ? n : kSlots;
+  if constexpr (!TAIL) {
+    // without a tail a side rarely holds 64 orders: then only chunk 0 takes part
+    if (LOB_LIKELY(nr < kWave)) {
+      const int at = popc(lt_mask(l, n) & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
+      Chunk v;
+      v.p = P;
+      v.q = Q;
+      v.o = oid;
+      v.h = hnd;
+      shift_up(S.c0, l > at);
+      put(S.c0, v, at);
+      st.n[SD] = n + 1;
+      return;
+    }
+  }
   // the orders ahead (price equal or better) form a prefix, so chunk 1 holds some
   // only when chunk 0 is all ahead: both counts add up without a test (without a
   // tail chunk 1 is rarely in use and is skipped while it is empty)
-  int pos = popc(ballot(l < nr) & ballot(SD == 1 ? S.c0.p >= P : S.c0.p <= P));
+  int pos = popc(lt_mask(l, nr) & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
   if (TAIL || LOB_UNLIKELY(nr > kWave))
-    pos += popc(ballot(l + kWave < nr) & ballot(SD == 1 ? S.c1.p >= P : S.c1.p <= P));
+    pos += popc(lt_mask(l + kWave, nr) & (SD == 1 ? ge_mask(S.c1.p, P) : le_mask(S.c1.p, P)));
   Chunk v;
   v.p = P;
   v.q = Q;
@@ -539,7 +563,7 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
   const int n = st.n[SD];
   const int nr = n < kSlots ? n : kSlots;
   int k = -1;
-  uint64_t m = ballot(l < nr) & ballot(S.c0.o == oid);
+  uint64_t m = lt_mask(l, nr) & eq_mask(S.c0.o, oid);
   if (LOB_LIKELY(m != 0)) {
     // the common case, an order in chunk 0 found by its id
     const int k0 = first_set(m);
@@ -554,7 +578,7 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
     return;
   }
   if (nr > kWave) {
-    m = ballot(l + kWave < nr) & ballot(S.c1.o == oid);
+    m = lt_mask(l + kWave, nr) & eq_mask(S.c1.o, oid);
     if (m) k = kWave + first_set(m);
   }
   int t = -1;  // TAIL: entry in the tail
@@ -562,11 +586,11 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
     if (k < 0 && n > kSlots) t = tail_find(n - kSlots, [&](int e) { return tl.a[e].z == oid; });
   }
   if (k < 0 && t < 0) {
-    m = ballot(l < nr) & ballot(S.c0.o <= -9000) & ballot(S.c0.p == price);
+    m = lt_mask(l, nr) & le_mask(S.c0.o, -9000) & eq_mask(S.c0.p, price);
     if (m) {
       k = first_set(m);
     } else if (nr > kWave) {
-      m = ballot(l + kWave < nr) & ballot(S.c1.o <= -9000) & ballot(S.c1.p == price);
+      m = lt_mask(l + kWave, nr) & le_mask(S.c1.o, -9000) & eq_mask(S.c1.p, price);
       if (m) k = kWave + first_set(m);
     }
     if constexpr (TAIL) {
