@@ -378,11 +378,11 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 
 // Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
 // with limit price lim and quantity q.  Returns the unfilled quantity.
-// EXTRA: the launch collects agent fills or per-message L2 (else those checks are
-// compiled out).  LIMIT: a limit order, which more often than not rests untouched
+// X: what the launch collects besides trades and final L2 -- bit 0 agent fills,
+// bit 1 per-message L2 (the checks for what it does not collect are compiled out).  LIMIT: a limit order, which more often than not rests untouched
 // (a layout hint only).
 // The aggressor is message j of the chunk v = (OID, TID, Ts, Tns) across the lanes.
-template <int OPP, bool TAIL, bool EXTRA, bool LIMIT>
+template <int OPP, bool TAIL, int X, bool LIMIT>
 __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, int q, const int4 &v, int j) {
   Side &S = side<OPP>(bk);
   const Tail &tl = bk.tl[OPP];
@@ -397,7 +397,7 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
     // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
     const int bo = rdlane(S.c0.o, 0);
     stage_one(st, sg, bp, q, bo, j, v);
-    if (EXTRA && st.fills)
+    if ((X & 1) && st.fills)
       fills_one(st, bp, q, bo, rdlane(v.x, j), rdlane(v.z, j), rdlane(v.w, j), (rdlane(S.c0.h, 0) & 1) != 0,
                 rdlane(v.y, j));
     if (q < bq) {
@@ -434,7 +434,7 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
       const int nfull = popc(mc & ballot(incl <= q));
       const int fill = takes ? min(qv, q - excl) : 0;
       stage_many(st, sg, ntr, F.p, fill, F.o, j, v);
-      if constexpr (EXTRA)
+      if constexpr ((X & 1) != 0)
         fills_many(st, takes, F.p, fill, F.o, rdlane(v.x, j), rdlane(v.z, j), rdlane(v.w, j), (F.h & 1) != 0,
                    rdlane(v.y, j));
       F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
@@ -691,10 +691,10 @@ __device__ __forceinline__ void write_l2(const Book &bk, const RState &st, int L
 
 // Handle of the order added by message k (j of the chunk v): 2k, plus 1 when the
 // launch collects agent fills and the message carries the agent's trader id.
-template <bool EXTRA>
+template <int X>
 __device__ __forceinline__ int handle(const RState &st, int k, const int4 &v, int j) {
   int h = k * 2;
-  if constexpr (EXTRA) h += (rdlane(v.y, j) == st.agent_tid) ? 1 : 0;
+  if constexpr ((X & 1) != 0) h += (rdlane(v.y, j) == st.agent_tid) ? 1 : 0;
   return h;
 }
 
@@ -707,7 +707,7 @@ __device__ __forceinline__ int handle(const RState &st, int k, const int4 &v, in
 // Message j of the chunk held as u = (type, side, P, Q), v = (oid, tid, ts, tns)
 // across the lanes, message k of the book's stream; each case reads only the
 // fields it uses.
-template <bool TAIL, bool EXTRA>
+template <bool TAIL, int X>
 __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int code, const int4 &u, const int4 &v,
                                             int j, int k) {
   // tested in order of frequency: limit orders, cancels, market orders
@@ -715,11 +715,11 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
     const int P = rdlane(u.z, j), Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 7
     if (code == 0) {
-      const int rem = match<1, TAIL, EXTRA, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<EXTRA>(st, k, v, j));
+      const int rem = match<1, TAIL, X, true>(bk, st, sg, P, Q, v, j);
+      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<X>(st, k, v, j));
     } else {
-      const int rem = match<0, TAIL, EXTRA, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<EXTRA>(st, k, v, j));
+      const int rem = match<0, TAIL, X, true>(bk, st, sg, P, Q, v, j);
+      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<X>(st, k, v, j));
     }
   } else if (code < 4) {
     if (code == 2)
@@ -729,15 +729,15 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
   } else if (code < 6) {
     const int Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);
-    const int rem = code == 4 ? match<1, TAIL, EXTRA, false>(bk, st, sg, 0, Q, v, j)
-                              : match<0, TAIL, EXTRA, false>(bk, st, sg, INT_MAX, Q, v, j);
+    const int rem = code == 4 ? match<1, TAIL, X, false>(bk, st, sg, 0, Q, v, j)
+                              : match<0, TAIL, X, false>(bk, st, sg, INT_MAX, Q, v, j);
     if (rem > 0) st.market_discarded += (unsigned)rem;
   }
 }
 
 // The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
 // form's agent orders) msgs2[beg2, beg2 + n2), in 64-message chunks.
-template <bool TAIL, bool EXTRA>
+template <bool TAIL, int X>
 __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, const ProcArgs &a, long long beg1,
                                             long long n1, long long beg2, long long n2, int32_t *l2_rows) {
   const int l = lane_id();
@@ -791,8 +791,8 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
 #pragma nounroll
     for (int j = 0; j < cnt; ++j) {
       const int c = rdlane(code, j);
-      process_msg<TAIL, EXTRA>(bk, st, sg, c, u, v, j, (int)k0 + j);
-      if constexpr (EXTRA) {
+      process_msg<TAIL, X>(bk, st, sg, c, u, v, j, (int)k0 + j);
+      if constexpr ((X & 2) != 0) {
         if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
       }
     }
@@ -801,14 +801,14 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
 }
 
 // Slot s (< n) of one side of the loaded book: its P, Q, OID and handle.
-template <bool EXTRA>
+template <bool FILLS>
 __device__ __forceinline__ Chunk load_slot(const int2 *base, int cap, int s, int agent_tid) {
   const int2 pq = base[s], ot = base[cap + s];
   Chunk x;
   x.p = pq.x;
   x.q = pq.y;
   x.o = ot.x;
-  x.h = (-1 - s) * 2 + ((EXTRA && ot.y == agent_tid) ? 1 : 0);
+  x.h = (-1 - s) * 2 + ((FILLS && ot.y == agent_tid) ? 1 : 0);
   return x;
 }
 
@@ -856,7 +856,7 @@ __device__ __forceinline__ void store_order(const Chunk &x, int2 *dst, const int
 }
 
 // TAIL form: tails of the two sides in LDS at `lds`, a.W entries each.
-template <bool TAIL, bool EXTRA>
+template <bool TAIL, int X>
 __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   const int l = lane_id();
   const int book = a.book_ids ? uni(a.book_ids[i]) : i;
@@ -914,10 +914,10 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   int2 *ob = a.books + off_out;
   const int cap = st.cap;
   Book bk;
-  load_chunk(bk.ask.c0, hb, cap, l, st.n[0], st.agent_tid, EXTRA);
-  load_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0], st.agent_tid, EXTRA);
-  load_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1], st.agent_tid, EXTRA);
-  load_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1], st.agent_tid, EXTRA);
+  load_chunk(bk.ask.c0, hb, cap, l, st.n[0], st.agent_tid, (X & 1) != 0);
+  load_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0], st.agent_tid, (X & 1) != 0);
+  load_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1], st.agent_tid, (X & 1) != 0);
+  load_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1], st.agent_tid, (X & 1) != 0);
   if constexpr (TAIL) {
     // slot s >= 128 of a side holding n orders is tail entry n - 1 - s
     for (int sd = 0; sd < 2; ++sd) {
@@ -925,7 +925,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
       t.a = reinterpret_cast<int4 *>(lds + sd * 2 * a.W);  // a.W int4 per side
       const int n = st.n[sd];
       const int2 *src = hb + (int64_t)sd * 3 * cap;
-      for (int s = kSlots + l; s < n; s += kWave) tail_put(t, n - 1 - s, load_slot<EXTRA>(src, cap, s, st.agent_tid));
+      for (int s = kSlots + l; s < n; s += kWave) tail_put(t, n - 1 - s, load_slot<(X & 1) != 0>(src, cap, s, st.agent_tid));
     }
   }
   Stage sg;
@@ -937,7 +937,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   // int32 apart per listed book
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
                      : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
-  process_all<TAIL, EXTRA>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
+  process_all<TAIL, X>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
   if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
   Streams ms;
@@ -983,13 +983,13 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   }
 }
 
-template <bool TAIL, bool EXTRA>
+template <bool TAIL, int X>
 __global__ void __launch_bounds__(1024) k_process_small(ProcArgs a) {
   extern __shared__ __align__(16) int2 tail_smem[];
   const int w = uni(threadIdx.x / kWave);  // uniform: one wave = one book
   const int i = blockIdx.x * a.bpb + w;
   if (i >= a.n) return;
-  run_book<TAIL, EXTRA>(a, i, TAIL ? tail_smem + (int64_t)w * a.lds_int2_per_wave : nullptr);
+  run_book<TAIL, X>(a, i, TAIL ? tail_smem + (int64_t)w * a.lds_int2_per_wave : nullptr);
 }
 
 __global__ void k_selftest_shift(int32_t *out) {
@@ -1013,24 +1013,33 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int threads = a.bpb * kWave;
   const int grid = (a.n + a.bpb - 1) / a.bpb;
   const size_t lds = tail ? (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2) : 0;
-  const bool extra = a.fills != nullptr || a.l2_mode == 1;
-  if (tail && extra)
-    hipLaunchKernelGGL((k_process_small<true, true>), dim3(grid), dim3(threads), lds, s, a);
-  else if (tail)
-    hipLaunchKernelGGL((k_process_small<true, false>), dim3(grid), dim3(threads), lds, s, a);
-  else if (extra)
-    hipLaunchKernelGGL((k_process_small<false, true>), dim3(grid), dim3(threads), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_process_small<false, false>), dim3(grid), dim3(threads), 0, s, a);
+  const int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0);
+  switch ((tail ? 4 : 0) | x) {
+#define LOB_SMALL_CASE(T, X)                                                                   \
+  case (T ? 4 : 0) | X:                                                                        \
+    hipLaunchKernelGGL((k_process_small<T, X>), dim3(grid), dim3(threads), T ? lds : 0, s, a); \
+    break;
+    LOB_SMALL_CASE(false, 0)
+    LOB_SMALL_CASE(false, 1)
+    LOB_SMALL_CASE(false, 2)
+    LOB_SMALL_CASE(false, 3)
+    LOB_SMALL_CASE(true, 0)
+    LOB_SMALL_CASE(true, 1)
+    LOB_SMALL_CASE(true, 2)
+    LOB_SMALL_CASE(true, 3)
+#undef LOB_SMALL_CASE
+  }
   return hipGetLastError();
 }
 
 hipError_t set_process_small_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_process_small<true, true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_process_small<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  const void *k[4] = {(const void *)k_process_small<true, 0>, (const void *)k_process_small<true, 1>,
+                      (const void *)k_process_small<true, 2>, (const void *)k_process_small<true, 3>};
+  for (const void *f : k) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_selftest_shift(int32_t *out, hipStream_t s) {
