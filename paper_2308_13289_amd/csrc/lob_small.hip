@@ -147,7 +147,7 @@ struct RState {
   int n[2];
   int cap, flags;
   int trades, misses;
-  long long limit_qty, market_qty, traded_qty, cancelled_qty, market_discarded, rejected_qty;
+  long long cancelled_qty, market_discarded, rejected_qty;
   int last_ts, last_tns, seen;
   int32_t *log;  // the book's next free log record, or nullptr
   int log_room;  // records that still fit in the log
@@ -163,6 +163,9 @@ struct RState {
 struct Stage {
   int p, q, po, j;
   int k;
+  // per-lane running sums of submitted limit and market quantities and of traded
+  // quantities, reduced over the wave once at the end of the call
+  unsigned long long limit_qty, market_qty, traded_qty;
 };
 
 // Sum over the wave of a non-negative int32 per lane, as 64-bit.
@@ -172,12 +175,17 @@ __device__ __forceinline__ long long wave_sum(int v) {
   return (long long)rdlane(lo, 63) + ((long long)rdlane(hi, 63) << 16);
 }
 
+// Sum over the wave of a 64-bit value per lane (the total below 2^63).
+__device__ __forceinline__ long long wave_sum64(unsigned long long v) {
+  return wave_sum((int)(unsigned)v) + (wave_sum((int)(unsigned)(v >> 32)) << 32);
+}
+
 // The pending trades are counted (trades and traded quantity) and stored; v holds
 // (OID, TID, Ts, Tns) of the chunk's messages across the lanes.
 __device__ __forceinline__ void flush(RState &st, Stage &sg, const int4 &v) {
   if (sg.k == 0) return;
   st.trades += sg.k;
-  st.traded_qty += wave_sum(lane_id() < sg.k ? sg.q : 0);
+  sg.traded_qty += (unsigned)(lane_id() < sg.k ? sg.q : 0);
   if (st.log) {
     const int stored = st.log_room < sg.k ? st.log_room : sg.k;
     const int l = lane_id();
@@ -783,8 +791,8 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
       st.seen = 1;
       // submitted quantity of limit and market orders (Q > 0 only)
       const int qpos = u.w > 0 ? u.w : 0;
-      st.limit_qty += wave_sum(code < 2 ? qpos : 0);
-      st.market_qty += wave_sum((code >> 1) == 2 ? qpos : 0);
+      sg.limit_qty += (unsigned)(code < 2 ? qpos : 0);
+      sg.market_qty += (unsigned)((code >> 1) == 2 ? qpos : 0);
     }
     // messages of this chunk that come from source 1 (they get per-message L2 rows)
     const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
@@ -872,7 +880,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   }
   st.flags = uni(h->flags);
   st.trades = st.misses = 0;
-  st.limit_qty = st.market_qty = st.traded_qty = st.cancelled_qty = st.market_discarded = st.rejected_qty = 0;
+  st.cancelled_qty = st.market_discarded = st.rejected_qty = 0;
   st.last_ts = uni(h->last_ts);
   st.last_tns = uni(h->last_tns);
   st.seen = uni(h->seen_time);
@@ -931,6 +939,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   Stage sg;
   sg.p = sg.q = sg.po = sg.j = 0;
   sg.k = 0;
+  sg.limit_qty = sg.market_qty = sg.traded_qty = 0;
 
   if (a.prio_len > 0 && n1 >= a.prio_len) __builtin_amdgcn_s_setprio(3);
   // per-message L2 rows of source 1: contiguous by message index, or l2_stride
@@ -962,6 +971,8 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     if (st.fill_count > st.fill_cap) st.flags |= kFlagFillsFull;
     if (l == 0 && a.fill_counts) a.fill_counts[row] = st.fill_count;
   }
+  const long long limit_qty = wave_sum64(sg.limit_qty), market_qty = wave_sum64(sg.market_qty),
+                  traded_qty = wave_sum64(sg.traded_qty);
   if (l == 0) {
     h->book_off = off_out;
     h->n[0] = st.n[0];
@@ -969,9 +980,9 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     h->flags = st.flags;
     h->n_msgs += n1 + n2;
     h->n_trades += st.trades;
-    h->limit_qty += st.limit_qty;
-    h->market_qty += st.market_qty;
-    h->traded_qty += st.traded_qty;
+    h->limit_qty += limit_qty;
+    h->market_qty += market_qty;
+    h->traded_qty += traded_qty;
     h->cancelled_qty += st.cancelled_qty;
     h->market_discarded += st.market_discarded;
     h->rejected_qty += st.rejected_qty;
