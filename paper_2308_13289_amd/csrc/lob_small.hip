@@ -289,6 +289,14 @@ __device__ __forceinline__ void shift_dn(Chunk &x, bool take) {
   x.h = take ? h : x.h;
 }
 
+// Every lane takes the next lane's order (lane 63 receives zeros).
+__device__ __forceinline__ void shift_dn_all(Chunk &x) {
+  x.p = dn1(x.p);
+  x.q = dn1(x.q);
+  x.o = dn1(x.o);
+  x.h = dn1(x.h);
+}
+
 __device__ __forceinline__ void shift_up(Chunk &x, bool take) {
   const int p = up1(x.p), q = up1(x.q), o = up1(x.o), h = up1(x.h);
   x.p = take ? p : x.p;
@@ -307,19 +315,30 @@ __device__ __forceinline__ void put(Chunk &x, const Chunk &v, int lane) {
 
 // Slots (k, n) of a side move down by one (slot k < 128 is dropped); in the TAIL
 // form the tail's last entry (slot 128) moves up into slot 127.
-template <bool TAIL>
+// FRONT: k is 0 (the best order), every lane moves without a select (used in the
+// TAIL form; without a tail the select form measured faster).
+template <bool TAIL, bool FRONT = false>
 __device__ __forceinline__ void remove_at(Side &S, const Tail &tl, int k, int n) {
   const int l = lane_id();
+  constexpr bool front = FRONT;
   if (TAIL ? LOB_LIKELY(n > kWave) : LOB_UNLIKELY(n > kWave)) {
     const Chunk in = edge(S.c1, 0);  // slot 64 moves to slot 63
-    shift_dn(S.c1, l + kWave >= k);
-    if (k < kWave) {
-      shift_dn(S.c0, l >= k);
+    if (front) {
+      shift_dn_all(S.c1);
+      shift_dn_all(S.c0);
       put(S.c0, in, 63);
+    } else {
+      shift_dn(S.c1, l + kWave >= k);
+      if (k < kWave) {
+        shift_dn(S.c0, l >= k);
+        put(S.c0, in, 63);
+      }
     }
     if constexpr (TAIL) {
       if (n > kSlots) pick(S.c1, l == 63, tail_get(tl, n - kSlots - 1));
     }
+  } else if (front) {
+    shift_dn_all(S.c0);
   } else {
     shift_dn(S.c0, l >= k);
   }
@@ -333,7 +352,7 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n);
 template <bool TAIL>
 __device__ __forceinline__ void remove_front(Side &S, const Tail &tl, int m, int n) {
   if (m == 1) {
-    remove_at<TAIL>(S, tl, 0, n);
+    remove_at<TAIL, TAIL>(S, tl, 0, n);
     return;
   }
   const int l = lane_id();
@@ -411,7 +430,7 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
     if (q < bq) {
       S.c0.q = wl(S.c0.q, bq - q, 0);
     } else {
-      remove_at<TAIL>(S, tl, 0, n);
+      remove_at<TAIL, TAIL>(S, tl, 0, n);
       st.n[OPP] = n - 1;
     }
     return 0;
