@@ -289,9 +289,10 @@ def bench_serving(args, n_books=20_000, lams=(50_000, 100_000, 200_000, 500_000)
     out = {"workload": f"{n_books} books, capacity {{50,100,500,1000}}, Poisson arrivals for "
                        f"{duration_s}s per rate, 50% replay / 50% step, 1..1000 msgs per request, "
                        f"4 batch slots, 1 GiB staging budget", "rates": []}
-    # untimed warm-up: the first launches load the kernels' code objects and the
-    # server's first batches allocate its staging
-    sw = S.ServingWorkload(n_books, lams[0], 0.05, threads=host_cores())
+    # untimed warm-up, a full run at the first rate: the first serving run in a
+    # process shows a tail (p99 12-17 ms at 50k req/s against 1 ms on a second run)
+    # that a 0.05 s warm-up did not remove
+    sw = S.ServingWorkload(n_books, lams[0], duration_s, threads=host_cores())
     ctx = lob.Context(sw.caps, l2_levels=LEVELS, trade_log_records=2 * sw.caps.astype(np.int64) + 2 * 1004)
     ctx.set_plan(lds_slots=128, books_per_block=2)
     srv = S.Server(ctx, n_slots=4, hbm_budget=1 << 30, max_batch=4096, max_request_msgs=1000, fill_cap=64)
