@@ -62,17 +62,20 @@ def kernel_name(ctx, w):
     return "k_process<true>" if int(w.caps.max()) > plan.lds_slots else "k_process<false>"
 
 
-def load_traffic(name, khash):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/<name>.json),
-    valid only for the kernel source they were taken on."""
+def load_profile(name, khash):
+    """The rocprofv3 counter figures of a kernel (profiles/<name>.traffic.json),
+    valid only for the kernel source they were taken on; {} otherwise."""
     p = os.path.join(ROOT, "profiles", f"{name}.traffic.json")
     if not os.path.exists(p):
-        return None
+        return {}
     with open(p) as f:
         d = json.load(f)
-    if d.get("kernel_hash") != khash:
-        return None
-    return d.get("hbm_bytes_per_launch")
+    return d if d.get("kernel_hash") == khash else {}
+
+
+def load_traffic(name, khash):
+    """HBM bytes per launch measured by rocprofv3 counters."""
+    return load_profile(name, khash).get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(w, n_sample_books):
@@ -159,6 +162,11 @@ def bench_uniform(args, w, desc):
     khash = kernel_source_hash()
     wl = "c1" if args.workload in ("all", "c1") else args.workload
     traffic = load_traffic(f"{kernel_name(ctx, w)}_{wl}", khash)
+    # the bound is instruction issue along each book's serial chain: issue counters
+    # of the same kernel beside the HBM fraction, and the waves per SIMD of this launch
+    issue = dict(load_profile(f"{kernel_name(ctx, w)}_{wl}", khash).get("issue", {}))
+    issue.pop("commands", None)
+    issue["waves_per_simd"] = w.n_books / (4 * torch.cuda.get_device_properties(0).multi_processor_count)
     res = {
         "metric": METRIC, "value": n_msgs * args.steps / wall, "unit": "msgs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -173,7 +181,7 @@ def bench_uniform(args, w, desc):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "kernel": kernel_name(ctx, w),
-                     "kernel_hash": khash},
+                     "kernel_hash": khash, "issue": issue},
         "h2d_s": h2d_s,
         "pcie_inclusive_msgs_per_s": n_msgs / (h2d_s + wall / args.steps),
     }
@@ -633,7 +641,7 @@ def main():
     res = bench_uniform(args, w, desc)
     log(f"timed {args.steps} steps: {res['ms_per_step']:.2f} ms/step, {res['value'] / 1e9:.3f} G msgs/s")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, 1024)
+        res["cpu_baseline"] = cpu_baseline(w, w.n_books)
         log(f"cpu baseline: {res['cpu_baseline']['value'] / 1e6:.2f} M msgs/s")
     del w
     if args.workload == "all":
