@@ -10,6 +10,7 @@ top-10 L2 of every book.  Prints ONE JSON line.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -46,11 +47,20 @@ KERNEL_SOURCES = ("paper_2308_13289_amd/csrc/lob_kernels.hip", "paper_2308_13289
                   "paper_2308_13289_amd/build.py")
 
 
+def _code_only(text):
+    """C/C++ source without comments or blank lines (a comment edit does not change
+    the kernel a profile was taken on)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            text = f.read()
+        h.update((text if p.endswith(".py") else _code_only(text)).encode())
     return h.hexdigest()[:16]
 
 

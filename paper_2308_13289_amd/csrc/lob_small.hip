@@ -13,12 +13,13 @@
 // shift (wave_shr:1 / wave_shl:1) with the neighbouring chunk's edge lane carried
 // in, and chunk 1 is left alone while the side holds at most 64 orders; removing
 // several leading orders at once is a ds_bpermute.  Trade records are staged one
-// per lane (lane k holds the k-th pending record) and stored to the log 64 at a
-// time, so a message that trades once costs six lane-selects and no store.
+// per lane (lane k holds the k-th pending record) and stored to the log when 64
+// are pending and at the end of every 64-message chunk, so a message that trades
+// once costs four lane-selects and no store.
 //
 // Per 64 messages the lanes decode the message cases, check that times do not
-// decrease and sum the submitted limit / market quantity; the scalar path per
-// message only dispatches on the case.
+// decrease and add the submitted limit / market quantity to per-lane sums; the
+// scalar path per message only dispatches on the case.
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <stdint.h>
