@@ -407,8 +407,8 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 // Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
 // with limit price lim and quantity q.  Returns the unfilled quantity.
 // X: what the launch collects besides trades and final L2 -- bit 0 agent fills,
-// bit 1 per-message L2 (the checks for what it does not collect are compiled out).  LIMIT: a limit order, which more often than not rests untouched
-// (a layout hint only).
+// bit 1 per-message L2 (the checks for what it does not collect are compiled out).
+// LIMIT: a limit order, which more often than not rests untouched (a layout hint).
 // The aggressor is message j of the chunk v = (OID, TID, Ts, Tns) across the lanes.
 template <int OPP, bool TAIL, int X, bool LIMIT>
 __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, int q, const int4 &v, int j) {
