@@ -583,8 +583,10 @@ __device__ __forceinline__ int tail_find(int T, Pred pred) {
 }
 
 // Cancel / delete (Section 4.1, item 2; Section 5.1.1 for initial orders) on side SD.
+// The message's price (lane j of pz, used only when no order has the id) is read on
+// that rare path alone.
 template <int SD, bool TAIL>
-__device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, int price) {
+__device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, int pz, int j) {
   Side &S = side<SD>(bk);
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
@@ -614,6 +616,8 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
     if (k < 0 && n > kSlots) t = tail_find(n - kSlots, [&](int e) { return tl.a[e].z == oid; });
   }
   if (k < 0 && t < 0) {
+    asm volatile("" : "+v"(pz));  // keeps the read below from being hoisted to the common path
+    const int price = rdlane(pz, j);
     m = lt_mask(l, nr) & le_mask(S.c0.o, -9000) & eq_mask(S.c0.p, price);
     if (m) {
       k = first_set(m);
@@ -751,9 +755,9 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
     }
   } else if (code < 4) {
     if (code == 2)
-      cancel<0, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
+      cancel<0, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), u.z, j);
     else
-      cancel<1, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), rdlane(u.z, j));
+      cancel<1, TAIL>(bk, st, rdlane(v.x, j), rdlane(u.w, j), u.z, j);
   } else if (code < 6) {
     const int Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);
