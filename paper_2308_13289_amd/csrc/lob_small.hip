@@ -147,6 +147,7 @@ __device__ __forceinline__ void pick(Chunk &x, bool c, const Chunk &v) {
 struct RState {
   int n[2];
   int cap, flags;
+  int small_lim;  // min(capacity, 64): below it an insert without a tail needs no other test
   int trades, misses;
   long long cancelled_qty, market_discarded, rejected_qty;
   int last_ts, last_tns, seen;
@@ -490,15 +491,10 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
   const int n = st.n[SD];
-  if (LOB_UNLIKELY(n >= st.cap)) {
-    st.rejected_qty += (unsigned)Q;
-    st.flags |= kFlagSideFull;
-    return;
-  }
-  const int nr = n < kSlots ? n : kSlots;
   if constexpr (!TAIL) {
-    // without a tail a side rarely holds 64 orders: then only chunk 0 takes part
-    if (LOB_LIKELY(nr < kWave)) {
+    // without a tail a side rarely holds 64 orders: then only chunk 0 takes part,
+    // and one test covers the capacity too
+    if (LOB_LIKELY(n < st.small_lim)) {
       const int at = popc(lt_mask(l, n) & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
       Chunk v;
       v.p = P;
@@ -511,6 +507,12 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
       return;
     }
   }
+  if (LOB_UNLIKELY(n >= st.cap)) {
+    st.rejected_qty += (unsigned)Q;
+    st.flags |= kFlagSideFull;
+    return;
+  }
+  const int nr = n < kSlots ? n : kSlots;
   // the orders ahead (price equal or better) form a prefix, so chunk 1 holds some
   // only when chunk 0 is all ahead: both counts add up without a test (without a
   // tail chunk 1 is rarely in use and is skipped while it is empty)
@@ -898,6 +900,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   st.n[0] = uni(h->n[0]);
   st.n[1] = uni(h->n[1]);
   st.cap = uni(h->cap);
+  st.small_lim = st.cap < kWave ? st.cap : kWave;
   if (st.cap > (TAIL ? kSlots + a.W : kSlots)) {  // not launched for such books; leave the book untouched
     if (l == 0) h->flags |= kFlagBadLoad;
     return;
