@@ -261,7 +261,7 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
   c->plan.lds_slots = c->max_cap <= 1024 ? c->max_cap : 256;
   c->plan.books_per_block = 4;
   c->plan.ragged_split = 0;
-  c->plan.lds_slots_big = c->max_cap;
+  c->plan.lds_slots_big = c->plan.lds_slots;  // (a valid plan: lob_set_plan accepts it back)
   c->plan.ragged_order = 1;
   c->plan.books_per_block_big = 1;
   c->plan.registers = 1;

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblob.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ECAP = 0, -1, -2, -3, -6
 L2_NONE, L2_PER_MESSAGE, L2_FINAL = 0, 1, 2
+MAX_CAPACITY, MAX_LEVELS = 4096, 64  # orders per side per book, L2 depth
 BOOK_SIDE_FULL, BOOK_TIME_ORDER, BOOK_TRADE_FULL, BOOK_FILLS_FULL, BOOK_BAD_LOAD = 1, 2, 4, 8, 16
 
 STATUS_DTYPE = np.dtype([(n, np.int64) for n in (

@@ -62,3 +62,14 @@ def test_create_rejects_bad_config_without_gpu_work(libpath):
     assert b"n_books" in L.lob_last_error(None)
     assert L.lob_process_messages(None, None, 0, None, None, 0, None, None) == lob.EINVAL
     assert L.lob_destroy(None) is None
+
+
+def test_binding_constants_match_the_header():
+    """Status codes, modes, flags and limits the binding spells out are the header's."""
+    from paper_2308_13289_amd import lob
+    text = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(LOB_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text)}
+    for name in ("OK", "EINVAL", "ENOMEM", "EDEVICE", "ECAP", "L2_NONE", "L2_PER_MESSAGE", "L2_FINAL",
+                 "MAX_CAPACITY", "MAX_LEVELS", "BOOK_SIDE_FULL", "BOOK_TIME_ORDER", "BOOK_TRADE_FULL",
+                 "BOOK_FILLS_FULL", "BOOK_BAD_LOAD"):
+        assert getattr(lob, name) == defs["LOB_" + name], name

@@ -206,6 +206,98 @@ def test_small_capacity_rejects_and_deep_books():
         assert_same(g, o, f"deep books {plan}")
 
 
+def deep_streams(caps, seed):
+    """Per book of capacity C: C + 40 resting orders on one side (the last ones
+    rejected once it is full), cancels and deletes of live, dead and rejected ids,
+    orders at both ends of the side, sweeps and market orders from the other side
+    that take up to a tenth of it each (across the register / tail boundary), then
+    mixed flow on both sides."""
+    rng = np.random.default_rng(seed)
+    streams = []
+    for b, C in enumerate(caps):
+        S = 1 if b % 2 == 0 else -1
+        ms, t, oid = [], 0, 0
+
+        def add(T, side, P, Q, o, tid=3):
+            nonlocal t
+            ms.append([T, side, P, Q, o, tid, 34200 + t // 1000, t % 1000])
+            t += 1
+
+        n1 = C + 40
+        for _ in range(n1):
+            oid += 1
+            add(1, S, int(rng.integers(900, 1000)), int(rng.integers(1, 50)), oid)
+        for _ in range(min(200, 2 * C + 4)):
+            if rng.random() < 0.8:
+                add(2, S, 0, int(rng.integers(1, 60)), int(rng.integers(1, n1 + 1)))
+            else:
+                add(3, S, 0, 100, int(rng.integers(1, n1 + 1)))
+        worst, best = (850, 1005) if S == 1 else (1050, 895)
+        for k in range(30):
+            oid += 1
+            add(1, S, worst if k % 2 == 0 else best, int(rng.integers(1, 50)), oid)
+        for _ in range(10):
+            oid += 1
+            add(1, -S, int(rng.integers(900, 1000)), int(rng.integers(C // 2 + 1, 2 * C + 2)), oid, tid=4)
+        for _ in range(3):
+            oid += 1
+            add(4, -S, 0, int(rng.integers(C // 2 + 1, C + 2)), oid, tid=4)
+        for _ in range(200):
+            r = rng.random()
+            if r < 0.6:
+                oid += 1
+                add(1, int(rng.choice([-1, 1])), int(rng.integers(940, 960)), int(rng.integers(1, 80)), oid)
+            else:
+                add(2, int(rng.choice([-1, 1])), 0, int(rng.integers(1, 80)), int(rng.integers(1, oid + 1)))
+        streams.append(ms)
+    msgs = np.array([m for s in streams for m in s], np.int32)
+    offs = np.concatenate([[0], np.cumsum([len(s) for s in streams])]).astype(np.int64)
+    return np.asarray(caps, np.int32), msgs, offs
+
+
+@pytest.mark.parametrize("group,plan", [
+    ("small", {}),
+    ("small", {"registers": 0}),
+    ("small", {"layout": 1}),
+    ("large", {}),
+    ("large", {"registers": 0}),
+    ("large", {"registers": 0, "lds_slots": 64}),
+    ("large", {"registers": 0, "lds_slots": 1024}),
+], ids=["small-regs", "small-lds", "small-unsorted", "large-regs-tail", "large-lds-spill256", "large-lds-spill64",
+        "large-lds-spill1024"])
+def test_extreme_capacities(group, plan):
+    """The smallest capacities, the edges of the register form (64, 128) and of the
+    register + tail form (129, 130), and the largest capacity the library accepts,
+    with sides filled to capacity and past it; per-message L2."""
+    caps = [1, 2, 3, 63, 64, 65, 127, 128] if group == "small" else [129, 130, 1000, 4095, lob.MAX_CAPACITY]
+    caps, msgs, offs = deep_streams(caps, seed=11 if group == "small" else 12)
+    g = run_gpu(caps, msgs, offs, l2_mode=lob.L2_PER_MESSAGE, plan=plan)
+    o = run_oracle(caps, msgs, offs, l2_mode=O.L2_PER_MESSAGE)
+    assert_same(g, o, f"{group} {plan}")
+    assert (o["stats"]["rejected_qty"] > 0).all() and (o["stats"]["cancel_miss"] > 0).all()
+
+
+def test_extreme_capacities_ragged():
+    """Both groups in one lob_process_ragged call, split into a register bucket and
+    a register + tail bucket."""
+    caps, msgs, offs = deep_streams([1, 2, 64, 128, 129, 1000, lob.MAX_CAPACITY], seed=13)
+    g = run_gpu(caps, msgs, offs, l2_mode=lob.L2_FINAL, plan={"ragged_split": 128}, ragged=True)
+    o = run_oracle(caps, msgs, offs, l2_mode=O.L2_FINAL)
+    assert_same(g, o, "extreme ragged")
+
+
+def test_plans_at_the_largest_capacity():
+    """The default plan of a context holding a book of the largest capacity is one
+    that lob_set_plan accepts back; the paper-layout form, which keeps a whole book
+    in LDS, is refused for such a context instead of being run."""
+    ctx = new_context([100, lob.MAX_CAPACITY], 10, [10, 10])
+    before = ctx.get_plan().as_dict()
+    assert ctx.set_plan().as_dict() == before
+    with pytest.raises(lob.LobError):
+        ctx.set_plan(layout=1)
+    assert ctx.get_plan().as_dict() == before
+
+
 def test_split_calls_equal_one_call():
     """Book state stays on the device between calls: three calls = one call."""
     w = W.uniform(48, 1500, tag=93)
