@@ -156,12 +156,28 @@ struct RState {
   int logged;    // records stored by this call
   int32_t *fills;
   int fill_cap, fill_count, agent_tid;
+  uint64_t agm;  // agent fills (kAgentMask): the chunk's messages that carry the agent's trader id
 };
+
+// Agent fills: whether message j of the chunk v = (OID, TID, Ts, Tns) carries the
+// agent's trader id -- a bit of the chunk's mask, or a lane read in the forms that
+// are short of scalar registers (a tail, per-message L2).
+template <bool TAIL, int X>
+constexpr bool kAgentMask = !TAIL && (X & 2) == 0;
+
+template <bool TAIL, int X>
+__device__ __forceinline__ bool agent_msg(const RState &st, const int4 &v, int j) {
+  if constexpr (kAgentMask<TAIL, X>)
+    return ((st.agm >> j) & 1) != 0;
+  else
+    return rdlane(v.y, j) == st.agent_tid;
+}
 
 // Pending trade records, one per lane; k of them (uniform) are pending.  A record
 // keeps the standing order's price, the fill and the standing id; the aggressor's
 // id and time are those of message j of the current chunk, fetched when the
-// records are stored, which happens at the latest when the chunk ends.
+// records are stored, which happens at the latest when the chunk ends.  When the
+// launch collects agent fills, bit 6 of j is set for a standing order of the agent.
 struct Stage {
   int p, q, po, j;
   int k;
@@ -183,15 +199,19 @@ __device__ __forceinline__ long long wave_sum64(unsigned long long v) {
 }
 
 // The pending trades are counted (trades and traded quantity) and stored; v holds
-// (OID, TID, Ts, Tns) of the chunk's messages across the lanes.
+// (OID, TID, Ts, Tns) of the chunk's messages across the lanes.  X bit 0: the
+// trades in which the agent takes part (a standing order of the agent, or an
+// aggressor carrying its trader id) are also stored as agent fills, in order.
+template <bool TAIL, int X>
 __device__ __forceinline__ void flush(RState &st, Stage &sg, const int4 &v) {
   if (sg.k == 0) return;
   st.trades += sg.k;
-  sg.traded_qty += (unsigned)(lane_id() < sg.k ? sg.q : 0);
+  const int l = lane_id();
+  sg.traded_qty += (unsigned)(l < sg.k ? sg.q : 0);
+  const int jj = (X & 1) != 0 ? (sg.j & 63) : sg.j;
   if (st.log) {
     const int stored = st.log_room < sg.k ? st.log_room : sg.k;
-    const int l = lane_id();
-    const int ao = from_lane(v.x, sg.j), ts = from_lane(v.z, sg.j), tns = from_lane(v.w, sg.j);
+    const int ao = from_lane(v.x, jj), ts = from_lane(v.z, jj), tns = from_lane(v.w, jj);
     if (l < stored) {
       int2 *r = reinterpret_cast<int2 *>(st.log + l * kTradeFields);
       r[0] = make_int2(sg.p, sg.q);
@@ -204,71 +224,73 @@ __device__ __forceinline__ void flush(RState &st, Stage &sg, const int4 &v) {
     st.logged += stored;
     lds_wait();  // the permutes are complete on every path out
   }
+  if constexpr ((X & 1) != 0) {
+    if (st.fills) {
+      bool agg;  // the aggressor carries the agent's trader id
+      if constexpr (kAgentMask<TAIL, X>) {
+        agg = ((st.agm >> jj) & 1) != 0;
+      } else {
+        agg = from_lane(v.y, jj) == st.agent_tid;
+        lds_wait();
+      }
+      const bool ag = (l < sg.k) & (agg | ((sg.j & 64) != 0));
+      const uint64_t ma = ballot(ag);
+      if (ma) {
+        const int ao = from_lane(v.x, jj), ts = from_lane(v.z, jj), tns = from_lane(v.w, jj);
+        const int f = st.fill_count + popc(ma & mask_lt());
+        if (ag && f < st.fill_cap) {
+          int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)f * kTradeFields);
+          r[0] = make_int2(sg.p, sg.q);
+          r[1] = make_int2(sg.po, ao);
+          r[2] = make_int2(ts, tns);
+        }
+        st.fill_count += popc(ma);
+        lds_wait();
+      }
+    }
+  }
   sg.k = 0;
 }
 
-// One trade from uniform values; the aggressor is message j of the chunk v.
+// One trade from uniform values; the aggressor is message j of the chunk v (with
+// bit 6 set for a standing order of the agent when the launch collects fills).
+template <bool TAIL, int X>
 __device__ __forceinline__ void stage_one(RState &st, Stage &sg, int P, int fill, int po, int j, const int4 &v) {
   sg.p = wl(sg.p, P, sg.k);
   sg.q = wl(sg.q, fill, sg.k);
   sg.po = wl(sg.po, po, sg.k);
   sg.j = wl(sg.j, j, sg.k);
-  if (LOB_UNLIKELY(++sg.k == kWave)) flush(st, sg, v);
+  if (LOB_UNLIKELY(++sg.k == kWave)) flush<TAIL, X>(st, sg, v);
 }
 
 // ntr trades held by lanes [0, ntr) (P, fill, standing id per lane; the aggressor
-// is message j of the chunk v): rotate them behind the pending ones.
-__device__ __forceinline__ void stage_many(RState &st, Stage &sg, int ntr, int P, int fill, int po, int j,
+// is message j of the chunk v): rotate them behind the pending ones.  pa: per lane,
+// the standing order is the agent's (used when the launch collects fills).
+template <bool TAIL, int X>
+__device__ __forceinline__ void stage_many(RState &st, Stage &sg, int ntr, int P, int fill, int po, int j, bool pa,
                                            const int4 &v) {
   const int l = lane_id();
   const int src = (l - sg.k) & 63;
   const int rp = from_lane(P, src), rq = from_lane(fill, src), ro = from_lane(po, src);
+  int rj = j;
+  if constexpr ((X & 1) != 0) rj = from_lane(j | (pa ? 64 : 0), src);
   const bool mine = l >= sg.k;
   sg.p = mine ? rp : sg.p;
   sg.q = mine ? rq : sg.q;
   sg.po = mine ? ro : sg.po;
-  sg.j = mine ? j : sg.j;
+  sg.j = mine ? rj : sg.j;
   const int end = sg.k + ntr;
   if (end >= kWave) {
     sg.k = kWave;
-    flush(st, sg, v);
+    flush<TAIL, X>(st, sg, v);
     sg.p = rp;
     sg.q = rq;
     sg.po = ro;
-    sg.j = j;
+    sg.j = rj;
     sg.k = end - kWave;
   } else {
     sg.k = end;
   }
-}
-
-// Agent fills (step form): trades where either side carries the agent's trader id.
-__device__ __forceinline__ void fills_one(RState &st, int P, int fill, int po, int ao, int ts, int tns, bool pag,
-                                          int atid) {
-  if (!st.fills || (!pag && atid != st.agent_tid)) return;
-  if (st.fill_count < st.fill_cap && lane_id() == 0) {
-    int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)st.fill_count * kTradeFields);
-    r[0] = make_int2(P, fill);
-    r[1] = make_int2(po, ao);
-    r[2] = make_int2(ts, tns);
-  }
-  st.fill_count++;
-}
-
-__device__ __forceinline__ void fills_many(RState &st, bool takes, int P, int fill, int po, int ao, int ts, int tns,
-                                           bool pag, int atid) {
-  if (!st.fills) return;
-  const bool ag = takes & (pag | (atid == st.agent_tid));
-  const uint64_t ma = ballot(ag);
-  if (ma == 0) return;
-  const int k = st.fill_count + popc(ma & mask_lt());
-  if (ag && k < st.fill_cap) {
-    int2 *r = reinterpret_cast<int2 *>(st.fills + (int64_t)k * kTradeFields);
-    r[0] = make_int2(P, fill);
-    r[1] = make_int2(po, ao);
-    r[2] = make_int2(ts, tns);
-  }
-  st.fill_count += popc(ma);
 }
 
 __device__ __forceinline__ Chunk edge(const Chunk &x, int lane) {  // uniform fields of one lane
@@ -451,10 +473,7 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
   if (LOB_LIKELY(q <= bq)) {
     // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
     const int bo = rdlane(S.c0.o, 0);
-    stage_one(st, sg, bp, q, bo, j, v);
-    if ((X & 1) && st.fills)
-      fills_one(st, bp, q, bo, rdlane(v.x, j), rdlane(v.z, j), rdlane(v.w, j), (rdlane(S.c0.h, 0) & 1) != 0,
-                rdlane(v.y, j));
+    stage_one<TAIL, X>(st, sg, bp, q, bo, (X & 1) != 0 ? j | ((rdlane(S.c0.h, 0) & 1) << 6) : j, v);
     if (q < bq) {
       S.c0.q = wl(S.c0.q, bq - q, 0);
     } else {
@@ -488,10 +507,7 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
       const bool full = cross & (incl <= q);
       const int nfull = popc(mc & ballot(incl <= q));
       const int fill = takes ? min(qv, q - excl) : 0;
-      stage_many(st, sg, ntr, F.p, fill, F.o, j, v);
-      if constexpr ((X & 1) != 0)
-        fills_many(st, takes, F.p, fill, F.o, rdlane(v.x, j), rdlane(v.z, j), rdlane(v.w, j), (F.h & 1) != 0,
-                   rdlane(v.y, j));
+      stage_many<TAIL, X>(st, sg, ntr, F.p, fill, F.o, j, (F.h & 1) != 0, v);
       F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
       const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
       q -= consumed;
@@ -751,10 +767,10 @@ __device__ __forceinline__ void write_l2(const Book &bk, const RState &st, int L
 
 // Handle of the order added by message k (j of the chunk v): 2k, plus 1 when the
 // launch collects agent fills and the message carries the agent's trader id.
-template <int X>
+template <bool TAIL, int X>
 __device__ __forceinline__ int handle(const RState &st, int k, const int4 &v, int j) {
   int h = k * 2;
-  if constexpr ((X & 1) != 0) h += (rdlane(v.y, j) == st.agent_tid) ? 1 : 0;
+  if constexpr ((X & 1) != 0) h += agent_msg<TAIL, X>(st, v, j) ? 1 : 0;
   return h;
 }
 
@@ -776,10 +792,10 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
     __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 7
     if (code == 0) {
       const int rem = match<1, TAIL, X, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<X>(st, k, v, j));
+      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j));
     } else {
       const int rem = match<0, TAIL, X, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<X>(st, k, v, j));
+      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j));
     }
   } else if (code < 4) {
     if (code == 2)
@@ -846,6 +862,7 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
       sg.limit_qty += (unsigned)(code < 2 ? qpos : 0);
       sg.market_qty += (unsigned)((code >> 1) == 2 ? qpos : 0);
     }
+    if constexpr ((X & 1) != 0 && kAgentMask<TAIL, X>) st.agm = ballot(v.y == st.agent_tid);
     // messages of this chunk that come from source 1 (they get per-message L2 rows)
     const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
 #pragma nounroll
@@ -856,7 +873,7 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
         if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
       }
     }
-    flush(st, sg, v);  // the staged records name messages of this chunk
+    flush<TAIL, X>(st, sg, v);  // the staged records name messages of this chunk
   }
 }
 
@@ -948,6 +965,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   st.fill_cap = a.fill_cap;
   st.fill_count = 0;
   st.agent_tid = a.agent_tid;
+  st.agm = 0;
 
   long long beg1 = 0, n1 = 0;
   if (a.msgs) {
