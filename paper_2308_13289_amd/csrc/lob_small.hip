@@ -811,32 +811,35 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
   }
 }
 
-// The book's messages: source 1 msgs[beg1, beg1 + n1), then source 2 (the step
-// form's agent orders) msgs2[beg2, beg2 + n2), in 64-message chunks.
+// Record k0 + lane of a book's stream -- source 1 msgs[beg1, beg1 + n1), then
+// source 2 (the step form's agent orders) msgs2[beg2, beg2 + n2) -- as u = (type,
+// side, P, Q) and v = (OID, TID, Ts, Tns); zeros past the stream's end.
+__device__ __forceinline__ void fetch_chunk(const ProcArgs &a, long long beg1, long long n1, long long beg2,
+                                            long long total, long long k0, int4 &u, int4 &v) {
+  const long long k = k0 + lane_id();
+  if (k < total) {
+    const int32_t *rec = k < n1 ? a.msgs + (beg1 + k) * kMsgFields : a.msgs2 + (beg2 + k - n1) * kMsgFields;
+    const int4 *mp = reinterpret_cast<const int4 *>(rec);
+    u = mp[0];
+    v = mp[1];
+  } else {
+    u = v = make_int4(0, 0, 0, 0);
+  }
+}
+
+// The book's messages in 64-message chunks, each loaded one chunk ahead of its use;
+// (un, vn) is the first chunk, already requested by the caller.
 template <bool TAIL, int X>
 __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, const ProcArgs &a, long long beg1,
-                                            long long n1, long long beg2, long long n2, int32_t *l2_rows) {
+                                            long long n1, long long beg2, long long n2, int32_t *l2_rows, int4 un,
+                                            int4 vn) {
   const int l = lane_id();
   const long long total = n1 + n2;
-  // record k0 + lane of the stream, loaded one chunk ahead of its use
-  auto fetch = [&](long long k0, int4 &u, int4 &v) {
-    const long long k = k0 + l;
-    if (k < total) {
-      const int32_t *rec = k < n1 ? a.msgs + (beg1 + k) * kMsgFields : a.msgs2 + (beg2 + k - n1) * kMsgFields;
-      const int4 *mp = reinterpret_cast<const int4 *>(rec);
-      u = mp[0];
-      v = mp[1];
-    } else {
-      u = v = make_int4(0, 0, 0, 0);
-    }
-  };
-  int4 un, vn;
-  fetch(0, un, vn);
 #pragma nounroll
   for (long long k0 = 0; k0 < total; k0 += kWave) {
     const int cnt = (int)((total - k0) < kWave ? (total - k0) : kWave);
     const int4 u = un, v = vn;
-    if (k0 + kWave < total) fetch(k0 + kWave, un, vn);
+    if (k0 + kWave < total) fetch_chunk(a, beg1, n1, beg2, total, k0 + kWave, un, vn);
     const int T = u.x, S = u.y;
     const bool ok = (l < cnt) & (T >= 1) & (T <= 4) & ((S == 1) | (S == -1));
     // code 7 also for Q <= 0: such a cancel removes nothing and such a limit or
@@ -889,9 +892,23 @@ __device__ __forceinline__ Chunk load_slot(const int2 *base, int cap, int s, int
   return x;
 }
 
+// Slots s (< n) of one side, zeros past the side's end.  FLAT: every lane loads (a
+// lane past the end reads slot 0, which every book has) and a select drops what is
+// not used; no load sits in a divergent branch, so the loads of all chunks are in
+// flight together (used without a tail, where a call is often short; the TAIL
+// form, short of scalar registers, keeps the branch).
+template <bool FLAT>
 __device__ __forceinline__ void load_chunk(Chunk &x, const int2 *base, int cap, int s, int n, int agent_tid,
                                            bool extra) {
-  if (s < n) {
+  const bool in = s < n;
+  if constexpr (FLAT) {
+    const Chunk y = extra ? load_slot<true>(base, cap, in ? s : 0, agent_tid)
+                          : load_slot<false>(base, cap, in ? s : 0, agent_tid);
+    x.p = in ? y.p : 0;
+    x.q = in ? y.q : 0;
+    x.o = in ? y.o : 0;
+    x.h = in ? y.h : 0;
+  } else if (in) {
     x = extra ? load_slot<true>(base, cap, s, agent_tid) : load_slot<false>(base, cap, s, agent_tid);
   } else {
     x.p = x.q = x.o = x.h = 0;
@@ -904,32 +921,60 @@ struct Streams {
   long long beg1, n1, beg2, total;
 };
 
-// Order x (one per lane) stored at slot s of one side of the written book `dst`;
-// its TID, Ts, Tns come through its handle from the stream or from the loaded
-// side `src` (the other buffer, not written by this launch).
-__device__ __forceinline__ void store_order(const Chunk &x, int2 *dst, const int2 *src, int cap, int s,
-                                            const Streams &m) {
-  long long idx = x.h >> 1;
-  int t, ts, tns;
-  if (idx >= 0) {
-    if (idx >= m.total) idx = m.total - 1;  // (cannot happen: a handle names a message of this stream)
-    const int32_t *rec = idx < m.n1 ? m.msgs + (m.beg1 + idx) * kMsgFields
-                                    : m.msgs2 + (m.beg2 + idx - m.n1) * kMsgFields;
-    const int4 r = reinterpret_cast<const int4 *>(rec)[1];  // (OID, TID, Ts, Tns)
-    t = r.y;
-    ts = r.z;
-    tns = r.w;
+// TID, Ts, Tns of order x (one per lane), found through its handle in the stream
+// or in the loaded side `src` (the other buffer, not written by this launch).
+// FLAT: the two sources are chosen by address and every lane loads (a lane without
+// an order, valid false, reads slot 0 of src), so that no load sits in a divergent
+// branch; otherwise only valid lanes call it and each source has its own loads.
+template <bool FLAT>
+__device__ __forceinline__ int4 order_meta(const Chunk &x, bool valid, const int2 *src, int cap, const Streams &m) {
+  long long idx = (!FLAT || valid) ? (x.h >> 1) : -1;
+  if constexpr (FLAT) {
+    const int32_t *pt;  // TID
+    const int2 *ptt;    // (Ts, Tns)
+    if (idx >= 0) {
+      if (idx >= m.total) idx = m.total - 1;  // (cannot happen: a handle names a message of this stream)
+      const int32_t *rec = idx < m.n1 ? m.msgs + (m.beg1 + idx) * kMsgFields
+                                      : m.msgs2 + (m.beg2 + idx - m.n1) * kMsgFields;
+      pt = rec + 5;
+      ptt = reinterpret_cast<const int2 *>(rec + 6);
+    } else {
+      int os = (int)(-1 - idx);
+      if (os >= cap) os = cap - 1;  // (cannot happen: a loaded slot is below the capacity)
+      pt = reinterpret_cast<const int32_t *>(src + cap + os) + 1;
+      ptt = src + 2 * cap + os;
+    }
+    const int t = *pt;
+    const int2 tt = *ptt;
+    return make_int4(t, tt.x, tt.y, 0);
   } else {
-    int os = (int)(-1 - idx);
-    if (os >= cap) os = cap - 1;  // (cannot happen: a loaded slot is below the capacity)
-    t = src[cap + os].y;
-    const int2 tt = src[2 * cap + os];
-    ts = tt.x;
-    tns = tt.y;
+    int t, ts, tns;
+    if (idx >= 0) {
+      if (idx >= m.total) idx = m.total - 1;
+      const int32_t *rec = idx < m.n1 ? m.msgs + (m.beg1 + idx) * kMsgFields
+                                      : m.msgs2 + (m.beg2 + idx - m.n1) * kMsgFields;
+      const int4 r = reinterpret_cast<const int4 *>(rec)[1];  // (OID, TID, Ts, Tns)
+      t = r.y;
+      ts = r.z;
+      tns = r.w;
+    } else {
+      int os = (int)(-1 - idx);
+      if (os >= cap) os = cap - 1;
+      t = src[cap + os].y;
+      const int2 tt = src[2 * cap + os];
+      ts = tt.x;
+      tns = tt.y;
+    }
+    return make_int4(t, ts, tns, 0);
   }
+}
+
+// Order x (one per lane) with its TID, Ts, Tns stored at slot s of one side of the
+// written book `dst`.
+__device__ __forceinline__ void put_order(const Chunk &x, const int4 &mt, int2 *dst, int cap, int s) {
   dst[s] = make_int2(x.p, x.q);
-  dst[cap + s] = make_int2(x.o, t);
-  dst[2 * cap + s] = make_int2(ts, tns);
+  dst[cap + s] = make_int2(x.o, mt.x);
+  dst[2 * cap + s] = make_int2(mt.y, mt.z);
 }
 
 // TAIL form: tails of the two sides in LDS at `lds`, a.W entries each.
@@ -938,6 +983,31 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   const int l = lane_id();
   const int book = a.book_ids ? uni(a.book_ids[i]) : i;
   if (book < 0 || book >= a.n_total) return;
+  // the book's messages: msgs[beg1, beg1 + n1), then msgs2 (the step form's agent
+  // orders) [i * w2, i * w2 + n2)
+  long long beg1 = 0, n1 = 0;
+  auto stream_range = [&]() {
+    if (a.msgs) {
+      if (a.ranges) {
+        beg1 = a.ranges[2 * i];
+        n1 = a.ranges[2 * i + 1] - beg1;
+      } else if (a.offs) {
+        beg1 = a.offs[i];
+        n1 = a.offs[i + 1] - beg1;
+      } else {
+        beg1 = (long long)i * a.w1;
+        n1 = a.w1;
+      }
+    }
+  };
+  const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
+  // without a tail the first message chunk is requested before the book's header
+  // and orders; the TAIL form, whose calls are long, requests it after them
+  int4 u0, v0;
+  if constexpr (!TAIL) {
+    stream_range();
+    fetch_chunk(a, beg1, n1, (long long)i * a.w2, n1 + n2, 0, u0, v0);
+  }
   BookHdr *h = a.hdr + book;
   RState st;
   st.n[0] = uni(h->n[0]);
@@ -967,20 +1037,8 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   st.agent_tid = a.agent_tid;
   st.agm = 0;
 
-  long long beg1 = 0, n1 = 0;
-  if (a.msgs) {
-    if (a.ranges) {
-      beg1 = a.ranges[2 * i];
-      n1 = a.ranges[2 * i + 1] - beg1;
-    } else if (a.offs) {
-      beg1 = a.offs[i];
-      n1 = a.offs[i + 1] - beg1;
-    } else {
-      beg1 = (long long)i * a.w1;
-      n1 = a.w1;
-    }
-  }
-  const long long n2 = (a.msgs2 && a.w2 > 0) ? a.w2 : 0;
+  if constexpr (TAIL) stream_range();
+
   if (n1 + n2 >= (1LL << 30)) {  // handles hold message indices below 2^30
     if (l == 0) h->flags |= kFlagBadLoad;
     return;
@@ -993,10 +1051,10 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   int2 *ob = a.books + off_out;
   const int cap = st.cap;
   Book bk;
-  load_chunk(bk.ask.c0, hb, cap, l, st.n[0], st.agent_tid, (X & 1) != 0);
-  load_chunk(bk.ask.c1, hb, cap, kWave + l, st.n[0], st.agent_tid, (X & 1) != 0);
-  load_chunk(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1], st.agent_tid, (X & 1) != 0);
-  load_chunk(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1], st.agent_tid, (X & 1) != 0);
+  load_chunk<!TAIL>(bk.ask.c0, hb, cap, l, st.n[0], st.agent_tid, (X & 1) != 0);
+  load_chunk<!TAIL>(bk.ask.c1, hb, cap, kWave + l, st.n[0], st.agent_tid, (X & 1) != 0);
+  load_chunk<!TAIL>(bk.bid.c0, hb + 3 * (int64_t)cap, cap, l, st.n[1], st.agent_tid, (X & 1) != 0);
+  load_chunk<!TAIL>(bk.bid.c1, hb + 3 * (int64_t)cap, cap, kWave + l, st.n[1], st.agent_tid, (X & 1) != 0);
   if constexpr (TAIL) {
     // slot s >= 128 of a side holding n orders is tail entry n - 1 - s
     for (int sd = 0; sd < 2; ++sd) {
@@ -1017,7 +1075,8 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   // int32 apart per listed book
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
                      : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
-  process_all<TAIL, X>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows);
+  if constexpr (TAIL) fetch_chunk(a, beg1, n1, (long long)i * a.w2, n1 + n2, 0, u0, v0);
+  process_all<TAIL, X>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows, u0, v0);
   if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
   Streams ms;
@@ -1027,15 +1086,37 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   ms.n1 = n1;
   ms.beg2 = (long long)i * a.w2;
   ms.total = n1 + n2;
-  for (int sd = 0; sd < 2; ++sd) {
-    const Side &S = sd == 0 ? bk.ask : bk.bid;
-    const int n = st.n[sd];
-    const int2 *src = hb + (int64_t)sd * 3 * cap;
-    int2 *dst = ob + (int64_t)sd * 3 * cap;
-    if (l < n) store_order(S.c0, dst, src, cap, l, ms);
-    if (kWave + l < n) store_order(S.c1, dst, src, cap, kWave + l, ms);
-    if constexpr (TAIL) {
-      for (int s = kSlots + l; s < n; s += kWave) store_order(tail_get(bk.tl[sd], n - 1 - s), dst, src, cap, s, ms);
+  if constexpr (!TAIL) {
+    // the orders' TID, Ts, Tns are all requested before any order is written (the
+    // written buffer may alias the read ones as far as the compiler knows)
+    int4 mt[2][2];
+    for (int sd = 0; sd < 2; ++sd) {
+      const Side &S = sd == 0 ? bk.ask : bk.bid;
+      const int n = st.n[sd];
+      const int2 *src = hb + (int64_t)sd * 3 * cap;
+      mt[sd][0] = order_meta<true>(S.c0, l < n, src, cap, ms);
+      mt[sd][1] = order_meta<true>(S.c1, kWave + l < n, src, cap, ms);
+    }
+    for (int sd = 0; sd < 2; ++sd) {
+      const Side &S = sd == 0 ? bk.ask : bk.bid;
+      const int n = st.n[sd];
+      int2 *dst = ob + (int64_t)sd * 3 * cap;
+      if (l < n) put_order(S.c0, mt[sd][0], dst, cap, l);
+      if (kWave + l < n) put_order(S.c1, mt[sd][1], dst, cap, kWave + l);
+    }
+  } else {
+    // long calls: the order of the loads does not matter; this form measured faster
+    for (int sd = 0; sd < 2; ++sd) {
+      const Side &S = sd == 0 ? bk.ask : bk.bid;
+      const int n = st.n[sd];
+      const int2 *src = hb + (int64_t)sd * 3 * cap;
+      int2 *dst = ob + (int64_t)sd * 3 * cap;
+      if (l < n) put_order(S.c0, order_meta<false>(S.c0, true, src, cap, ms), dst, cap, l);
+      if (kWave + l < n) put_order(S.c1, order_meta<false>(S.c1, true, src, cap, ms), dst, cap, kWave + l);
+      for (int s = kSlots + l; s < n; s += kWave) {
+        const Chunk x = tail_get(bk.tl[sd], n - 1 - s);
+        put_order(x, order_meta<false>(x, true, src, cap, ms), dst, cap, s);
+      }
     }
   }
   if (st.fills) {
