@@ -203,7 +203,7 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
 /* Autotuner for lob_process_ragged: runs the batch under candidate plans -- one
  * launch or two capacity buckets, LDS window sizes (books larger than the window
  * keep their tail in HBM), books per workgroup -- times each candidate with HIP
- * events on `stream` as the median of three runs after one untimed run, installs
+ * events on `stream` as the slowest of three runs after one untimed run, installs
  * the fastest plan in the context and returns it with that time.  Every run
  * starts from empty books: the listed books are reset before each run and left
  * reset at the end (their previous state is lost).  At most max_trials candidates

@@ -454,8 +454,10 @@ lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32
   int trials = 0;
   float best_t = 1e30f;
   lob_plan best_p = base;
-  // a candidate's time: the median of three runs after an untimed one (some plans
-  // vary from run to run; one run can pick a plan whose typical time is worse)
+  // a candidate's time: the slowest of three runs after an untimed one.  Some plans
+  // are bimodal from run to run (the two bucket launches race for the GPU's wave
+  // slots, and the longest book can start late); ranking by the worst run favours
+  // plans that are fast every time.
   auto trial = [&](lob_plan p) -> lob_status {
     if (trials >= max_trials) return LOB_OK;
     if (lob_set_plan(ctx, &p) != LOB_OK) return LOB_OK;  // candidate does not fit: skip it
@@ -475,8 +477,7 @@ lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32
       (void)hipEventElapsedTime(&ms, e0, e1);
     }
     if ((r = reset_listed()) != LOB_OK) return r;
-    std::sort(t, t + 3);
-    const float ms = t[1];
+    const float ms = std::max(t[0], std::max(t[1], t[2]));
     if (ms < best_t) {
       best_t = ms;
       best_p = p;
