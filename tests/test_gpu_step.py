@@ -107,8 +107,11 @@ def check_against_oracle(l2, fills, counts, ol2, ofills, F):
             np.testing.assert_array_equal(fills[s, b, :k], want[:k], err_msg=f"step {s} book {b}")
 
 
-def test_step_eager_matches_oracle():
-    w, seed_blk, windows, actions = step_case(48, 25)
+@pytest.mark.parametrize("cap", [100, 300, 1000], ids=["registers", "tail300", "tail1000"])
+def test_step_eager_matches_oracle(cap):
+    """Capacity 100 runs the register kernel's fills form; 300 and 1000 the form
+    with an LDS tail (a book seeded with cap/2 orders per side)."""
+    w, seed_blk, windows, actions = step_case(48, 25, cap=cap)
     F = 64
     R = StepRunner(w.caps, seed_blk, windows, actions, F=F)
     R.seed()
