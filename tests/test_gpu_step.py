@@ -181,3 +181,38 @@ def test_step_window_padding_and_no_actions():
     torch.cuda.synchronize()
     ol2, _ = oracle_steps(w.caps, seed_blk, windows, no_act)
     np.testing.assert_array_equal(l2.cpu().numpy(), ol2)
+
+
+@pytest.mark.parametrize("cap", [100, 300], ids=["registers", "tail"])
+def test_step_sweeps_store_fills_mid_chunk(cap):
+    """A data message that trades with 80 standing orders, more than the 64 trade
+    records staged at once (every third standing order is the agent's), and agent
+    market orders after it: fills are stored from the middle of a chunk as well as
+    at its end, in trade order."""
+    n, width = 4, 100
+    windows = np.zeros((n, 2, width, 8), np.int32)
+    actions = np.zeros((n, 2, 4, 8), np.int32)
+    for b in range(n):
+        side = -1 if b % 2 == 0 else 1  # the resting side: asks for even books
+        t, oid = 0, 1
+        for s, (rest, sweep) in enumerate([(90, 80 + b), (70, 66)]):
+            for k in range(rest):
+                price = 1000 + k if side == -1 else 1000 - k
+                tid = AGENT if k % 3 == 0 else 7
+                windows[b, s, k] = [1, side, price, 1, oid, tid, 34200, t]
+                oid, t = oid + 1, t + 1
+            windows[b, s, rest] = [4, -side, 0, sweep, oid, 9, 34200, t]  # a data market order
+            oid, t = oid + 1, t + 1
+            actions[b, s, 0] = [4, -side, 0, 5 + s, oid, AGENT, 34200, t]
+            actions[b, s, 1] = [1, side, 1000, 3, oid + 1, AGENT, 34200, t + 1]
+            oid, t = oid + 2, t + 2
+    seed_blk = np.zeros((n, 1, 8), np.int32)  # one padding message (type 0) per book
+    caps = np.full(n, cap, np.int32)
+    F = 64
+    R = StepRunner(caps, seed_blk, windows, actions, F=F)
+    R.seed()
+    R.run_steps()
+    l2, fills, counts = R.outputs()
+    ol2, ofills = oracle_steps(caps, seed_blk, windows, actions)
+    assert min(len(ofills[0][b]) for b in range(n)) > 25  # agent fills on both sides of the sweep
+    check_against_oracle(l2, fills, counts, ol2, ofills, F)
