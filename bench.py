@@ -612,8 +612,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(books shard across GPUs with no communication; see DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 "
+                                   "(books shard across GPUs with no communication between them)"}))
         sys.exit(2)
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))

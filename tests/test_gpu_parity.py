@@ -29,7 +29,7 @@ from test_oracle_bruteforce import alphabet, to_msgs  # noqa: E402
 # it was withdrawn and ragged batches use lob_process_ragged instead.  Its cases
 # stay here, skipped.
 WITHDRAWN = pytest.mark.skip(reason="persistent work-queue kernel withdrawn: its first GPU run "
-                                    "faulted and the cause was not found; see DESIGN.md")
+                                    "faulted and the cause was not found")
 
 
 def test_selftest_primitives():
