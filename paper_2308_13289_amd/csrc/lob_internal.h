@@ -82,6 +82,10 @@ struct ProcArgs {
   // priority (0: none); ragged calls set it so the longest streams, the critical
   // path, are not slowed by the short ones sharing their compute unit
   int64_t prio_len;
+  // 1: with prio_len 0, the register kernel's waves rotate their issue priority
+  // (set by the host when a launch has more books than the GPU has SIMDs, so that
+  // waves share SIMDs)
+  int32_t rotate;
 };
 
 }  // namespace lob

@@ -456,7 +456,8 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 // Matching loop of Section 4.1 against side OPP (0 asks, 1 bids) for an aggressor
 // with limit price lim and quantity q.  Returns the unfilled quantity.
 // X: what the launch collects besides trades and final L2 -- bit 0 agent fills,
-// bit 1 per-message L2 (the checks for what it does not collect are compiled out).
+// bit 1 per-message L2 (the checks for what it does not collect are compiled out);
+// bit 2 selects the rotating-priority variant.
 // LIMIT: a limit order, which more often than not rests untouched (a layout hint).
 // The aggressor is message j of the chunk v = (OID, TID, Ts, Tns) across the lanes.
 template <int OPP, bool TAIL, int X, bool LIMIT>
@@ -811,6 +812,22 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
   }
 }
 
+// Fair issue among the waves of a SIMD.  The instruction arbiter favours the oldest
+// wave, so of several books sharing a SIMD one runs ahead and the last one ends
+// alone, at one wave's speed.  With rank >= 0 a wave's priority rotates with time
+// (an epoch of 2^13 ticks of the 100 MHz real-time counter, about 82 us), offset by
+// its rank, so that each wave holds the highest priority a quarter of the time.
+// Compiled in only where it runs (X bit 2): the code alone slows a lone wave.
+__device__ __forceinline__ void rotate_priority(int rank) {
+  const unsigned epoch = (unsigned)(__builtin_amdgcn_s_memrealtime() >> 13);
+  switch ((epoch + (unsigned)rank) & 3) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+  }
+}
+
 // Record k0 + lane of a book's stream -- source 1 msgs[beg1, beg1 + n1), then
 // source 2 (the step form's agent orders) msgs2[beg2, beg2 + n2) -- as u = (type,
 // side, P, Q) and v = (OID, TID, Ts, Tns); zeros past the stream's end.
@@ -832,11 +849,12 @@ __device__ __forceinline__ void fetch_chunk(const ProcArgs &a, long long beg1, l
 template <bool TAIL, int X>
 __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, const ProcArgs &a, long long beg1,
                                             long long n1, long long beg2, long long n2, int32_t *l2_rows, int4 un,
-                                            int4 vn) {
+                                            int4 vn, int rank) {
   const int l = lane_id();
   const long long total = n1 + n2;
 #pragma nounroll
   for (long long k0 = 0; k0 < total; k0 += kWave) {
+    if constexpr ((X & 4) != 0) rotate_priority(rank);
     const int cnt = (int)((total - k0) < kWave ? (total - k0) : kWave);
     const int4 u = un, v = vn;
     if (k0 + kWave < total) fetch_chunk(a, beg1, n1, beg2, total, k0 + kWave, un, vn);
@@ -1070,13 +1088,18 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   sg.k = 0;
   sg.limit_qty = sg.market_qty = sg.traded_qty = 0;
 
+  // ragged launches raise the longest streams' waves for good; launches whose waves
+  // share SIMDs (X bit 2) rotate priorities (rank: the wave's slot on its SIMD, bits
+  // 3:0 of the HW_ID register)
   if (a.prio_len > 0 && n1 >= a.prio_len) __builtin_amdgcn_s_setprio(3);
+  int rank = 0;
+  if constexpr ((X & 4) != 0) rank = (int)(__builtin_amdgcn_s_getreg((3 << 11) | 4) & 3);
   // per-message L2 rows of source 1: contiguous by message index, or l2_stride
   // int32 apart per listed book
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
                      : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
   if constexpr (TAIL) fetch_chunk(a, beg1, n1, (long long)i * a.w2, n1 + n2, 0, u0, v0);
-  process_all<TAIL, X>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows, u0, v0);
+  process_all<TAIL, X>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows, u0, v0, rank);
   if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
   Streams ms;
@@ -1176,16 +1199,22 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int threads = a.bpb * kWave;
   const int grid = (a.n + a.bpb - 1) / a.bpb;
   const size_t lds = tail ? (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2) : 0;
-  const int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0);
-  switch ((tail ? 4 : 0) | x) {
+  // X: bit 0 agent fills, bit 1 per-message L2, bit 2 rotating priorities (without a
+  // tail only)
+  const int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0) | (!tail && a.rotate ? 4 : 0);
+  switch ((tail ? 8 : 0) | x) {
 #define LOB_SMALL_CASE(T, X)                                                                   \
-  case (T ? 4 : 0) | X:                                                                        \
+  case (T ? 8 : 0) | X:                                                                        \
     hipLaunchKernelGGL((k_process_small<T, X>), dim3(grid), dim3(threads), T ? lds : 0, s, a); \
     break;
     LOB_SMALL_CASE(false, 0)
     LOB_SMALL_CASE(false, 1)
     LOB_SMALL_CASE(false, 2)
     LOB_SMALL_CASE(false, 3)
+    LOB_SMALL_CASE(false, 4)
+    LOB_SMALL_CASE(false, 5)
+    LOB_SMALL_CASE(false, 6)
+    LOB_SMALL_CASE(false, 7)
     LOB_SMALL_CASE(true, 0)
     LOB_SMALL_CASE(true, 1)
     LOB_SMALL_CASE(true, 2)
