@@ -97,9 +97,15 @@ lob_status geometry(lob_ctx *c, int window, int cap_limit, int bpb_want, Geometr
 // the plan allows it and every such book fits in registers, else the LDS kernel.
 lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bpb, hipStream_t s) {
   if (a.n == 0) return LOB_OK;
-  // more books than SIMDs: waves share SIMDs and the register kernel rotates their
-  // issue priorities (one wave per SIMD has nothing to share)
-  a.rotate = (a.prio_len == 0 && (int64_t)a.n > 4 * (int64_t)c->num_cus) ? 1 : 0;
+  // waves sharing SIMDs: the register kernel rotates their issue priorities.  Measured
+  // on uniform books: a gain at 2 to 4 waves per SIMD, and for steps (short fixed
+  // windows) at 8; a loss for long streams at 8 or more waves per SIMD.  One wave per
+  // SIMD has nothing to share.
+  {
+    const int64_t simds = 4 * (int64_t)c->num_cus, n = a.n;
+    const bool step = a.msgs && !a.offs && !a.ranges;  // fixed windows of w1 messages
+    a.rotate = (a.prio_len == 0 && n > simds && (n <= 4 * simds || step)) ? 1 : 0;
+  }
   if (c->plan.layout == 1) {  // the paper's unsorted arrays, whole book in LDS
     const int per_wave = (lob::unsorted_lds_ints(cap_limit) + 1) / 2;
     int b = std::max(1, std::min(16, bpb));
