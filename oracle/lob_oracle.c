@@ -30,7 +30,14 @@
  *       level with the level's summed quantity; the ids -9000, -9001, ... are
  *       handed out level by level, ask before bid, the column order of a LOBSTER
  *       order-book row.  The paper leaves trader id and time of these orders open:
- *       both are arguments.  A snapshot that is not a valid book is refused.
+ *       both are arguments.  A snapshot that is not a valid book is refused.  The
+ *       initial orders' time counts as the book's latest time, so a later message
+ *       stamped before it is flagged like any other time going backwards (R2).
+ *   R19 Quantities are int32 (Section 4.2).  Matching, cancels and the counters
+ *       stay exact for every int32 quantity (the counters are int64).  An L2
+ *       level's summed quantity, which can pass INT32_MAX, is summed exactly and
+ *       reported as min(sum, INT32_MAX): the L2 record is int32 and the paper does
+ *       not define a level beyond it.
  */
 #include "lob_oracle.h"
 
@@ -281,11 +288,11 @@ void orc_l2(const orc_book *b, int32_t levels, int32_t *out) {
         o[1] = 0;
         continue;
       }
-      int32_t qsum = 0;
+      int64_t qsum = 0; /* R19 */
       for (int32_t i = 0; i < b->N; ++i)
         if (!is_empty(&side[i]) && side[i].f[P] == px) qsum += side[i].f[Q];
       o[0] = px;
-      o[1] = qsum;
+      o[1] = qsum > INT32_MAX ? INT32_MAX : (int32_t)qsum;
       prev = px;
       have_prev = 1;
     }
@@ -323,8 +330,10 @@ int32_t orc_seed_l2(orc_book *b, const int32_t *l2, int32_t levels, int32_t tid,
   }
   memset(&b->st, 0, sizeof(b->st));
   b->next_arrival = 0;
-  b->seen_time = 0;
-  b->last_ts = b->last_tns = 0;
+  /* R14: the initial orders' time is the book's latest time */
+  b->seen_time = 1;
+  b->last_ts = ts;
+  b->last_tns = tns;
   /* is it a book?  strictly ordered prices per side, room for every level, not crossed */
   int ok = 1;
   int32_t best_px[2] = {0, 0};

@@ -31,7 +31,8 @@
  *              with the standing order's id before the aggressor's; the last two
  *              let callers pick out fills that involve a given trader.
  *   L2       : [2][levels][2] = {asks, bids} x level x {price, qty}; a missing
- *              level is (-1, 0).
+ *              level is (-1, 0); a level's quantity is its exact sum capped at
+ *              INT32_MAX (R19 in lob_oracle.c).
  *   book dump: [cap][6] per side in priority order, unused rows all -1.
  */
 #ifndef LOB_ORACLE_H
@@ -96,7 +97,8 @@ int32_t orc_capacity(const orc_book *b);
  * 0 asks (best first, ascending prices), side 1 bids (best first, descending), each
  * entry (price, qty); entries with qty <= 0 are missing levels.  The book is
  * emptied and its counters cleared, then every present level becomes one order
- * holding the level's quantity, with trader id `tid` and time (ts, tns).  Order ids
+ * holding the level's quantity, with trader id `tid` and time (ts, tns), which also
+ * becomes the book's latest time for the time-order check.  Order ids
  * start at -9000 and descend, level by level, ask before bid (R14).  A snapshot
  * that is not a book -- prices not strictly ordered, bid >= ask, or more levels
  * than the capacity on a side -- leaves the book empty, sets ORC_FLAG_BAD_LOAD and

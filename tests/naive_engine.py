@@ -98,6 +98,7 @@ class NaiveBook:
             for o in self.sides[side]:
                 agg[o.price] = agg.get(o.price, 0) + o.qty
             prices = sorted(agg, reverse=(side == 1))[:levels]
-            rows = [[p, agg[p]] for p in prices] + [[-1, 0]] * (levels - len(prices))
+            # the L2 record is int32: a level's exact sum is reported capped at INT32_MAX
+            rows = [[p, min(agg[p], INT32_MAX)] for p in prices] + [[-1, 0]] * (levels - len(prices))
             out.append(rows)
         return out

@@ -38,6 +38,12 @@ MUTANTS = [
      "for (int sd = 0; sd < 2; ++sd) {\n    for (int32_t l = 0; l < levels; ++l) {"),
     ("seed_accepts_locked_book", "if (best_px[1] >= best_px[0]) ok = 0;", "if (best_px[1] > best_px[0]) ok = 0;"),
     ("seed_ids_ascending", "own[slot].f[OID] = oid--;", "own[slot].f[OID] = oid++;"),
+    ("l2_sum_in_int32", "int64_t qsum = 0; /* R19 */", "int32_t qsum = 0; /* R19 */"),
+    ("l2_sum_not_capped", "o[1] = qsum > INT32_MAX ? INT32_MAX : (int32_t)qsum;", "o[1] = (int32_t)qsum;"),
+    ("time_ignored_at_equal_price",
+     "if (x->f[TS] != y->f[TS]) return x->f[TS] < y->f[TS];\n  if (x->f[TNS] != y->f[TNS]) return x->f[TNS] < y->f[TNS];",
+     ""),
+    ("seed_time_not_latest", "b->seen_time = 1;\n  b->last_ts = ts;", "b->seen_time = 0;\n  b->last_ts = ts;"),
 ]
 
 PIN_TESTS = ["tests/test_oracle_golden.py", "tests/test_oracle_bruteforce.py::test_random_sequences",

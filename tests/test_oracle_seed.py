@@ -90,3 +90,21 @@ def test_seeded_orders_take_the_initial_order_cancel_rule():
     b.process([3, 1, 99, 3, 556, 1, 34201, 1])     # delete the whole bid level
     assert len(b.dump(1)) == 0
     assert b.stats()["cancel_miss"] == 0 and b.stats()["cancelled_qty"] == 7
+
+
+def test_seed_time_is_the_books_latest_time():
+    """R14: the initial orders' time is the book's latest time.  A message stamped
+    before it is flagged as time going backwards, and at an equal price it ranks
+    ahead of the seeded order (Section 4.1: earliest time first); one stamped at
+    it leaves the book unflagged and ranks behind (equal times: arrival order)."""
+    b = O.Book(8)
+    b.seed_l2(snap([(101, 5)], [(99, 3)], 2), tid=4, ts=34200, tns=17)
+    b.process([1, 1, 99, 2, 1, 1, 34200, 17])
+    assert b.stats()["flags"] == 0
+    np.testing.assert_array_equal(b.dump(1)[:, 2], [-9001, 1])
+    b = O.Book(8)
+    b.seed_l2(snap([(101, 5)], [(99, 3)], 2), tid=4, ts=34200, tns=17)
+    b.process([1, 1, 99, 6, 2, 1, 34200, 16])
+    assert b.stats()["flags"] & O.FLAG_TIME_ORDER
+    np.testing.assert_array_equal(b.dump(1)[:, 2], [2, -9001])
+    np.testing.assert_array_equal(b.l2(1)[1], [[99, 9]])
