@@ -44,6 +44,7 @@ def host_cores():
 
 KERNEL_SOURCES = ("paper_2308_13289_amd/csrc/lob_kernels.hip", "paper_2308_13289_amd/csrc/lob_small.hip",
                   "paper_2308_13289_amd/csrc/lob_device.h", "paper_2308_13289_amd/csrc/lob_internal.h",
+                  "paper_2308_13289_amd/csrc/lob_lds_engine.h",
                   "paper_2308_13289_amd/build.py")
 
 

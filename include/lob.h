@@ -30,15 +30,18 @@
  *       (Section 4.2, eq. "message") with price stored before qty.  type: 1 limit,
  *       2 cancel, 3 delete, 4 market; any other type is skipped (zero padding,
  *       Section 5.1.1).  side: +1 bid (buy), -1 ask (sell); any other side is
- *       skipped.  price is ignored for market orders.  Times must not decrease
- *       within a book (equal times keep arrival order); a decrease is flagged.
+ *       skipped.  price is ignored for market orders.  Times are expected not to
+ *       decrease within a book; a decrease is flagged (LOB_BOOK_TIME_ORDER) and
+ *       the results stay exact: priority among equal prices always follows the
+ *       time stamps (Section 4.1), equal times keep arrival order.
  *   trade (6 x int32)    {price, qty, passive_id, aggressive_id, time_s, time_ns}
  *       The trade t_j of Section 4.1 (eq. "trade"): the standing order's price,
  *       the traded quantity, both order ids (standing first) and the aggressor's
  *       time.
  *   L2 snapshot          int32 [2][levels][2] = {asks, bids} x level x {price, qty}
  *       Distinct prices best first (asks ascending, bids descending) with the
- *       summed quantity of the orders at that price; a missing level is (-1, 0).
+ *       summed quantity of the orders at that price, summed exactly and reported
+ *       as min(sum, INT32_MAX) (the record is int32); a missing level is (-1, 0).
  *   book dump            int32 [2][dump_cap][6] = {asks, bids} x order x
  *       {P, Q, OID, TID, Ts, Tns} (Section 4, eq. "features") in price-time
  *       priority; unused rows are -1 (the paper's empty marker).
@@ -53,7 +56,13 @@
  * with that id on the message's side (or, if there is none, from the best-priority
  * initial order -- id <= -9000 -- at the message's price, Section 5.1.1) and remove
  * it once its quantity is <= 0; a quantity <= 0 does nothing.  The best standing
- * order is the lowest ask / highest bid, earliest arrival first (eq. "best_price").
+ * order is the lowest ask / highest bid, earliest (Ts, Tns) first, then earliest
+ * arrival (eq. "best_price" and the text before it).
+ *
+ * Input domain: every int32 value of every field.  Quantities are int32 shares
+ * (Section 4.2); matching, cancels and trades are exact for any of them, including
+ * sweeps whose fills add up past INT32_MAX, and the counters of lob_book_status
+ * are int64.  Only an L2 level's summed quantity is capped (see above).
  */
 #ifndef LOB_H
 #define LOB_H
@@ -148,8 +157,11 @@ typedef struct {
 
 typedef struct lob_ctx lob_ctx;
 
-/* Create a context on cfg->device: every book empty, every trade log empty.  All
- * device memory the context uses is allocated here (books, trade logs, queues).
+/* Create a context on cfg->device: n_books books, book i with room for
+ * capacity_host[i] orders per side -- the fixed-size order arrays of Section 4
+ * (eq. "features"), whose empty positions are all -1 -- every book empty, every
+ * trade log empty, L2 snapshots of l2_levels levels (Section 5.1.1 uses 10).  All
+ * device memory the context uses is allocated here (books, trade logs, staging).
  * Returns LOB_EINVAL (bad config), LOB_ENOMEM or LOB_EDEVICE; *out is NULL then. */
 lob_status lob_create(const lob_config *cfg, lob_ctx **out);
 
@@ -228,7 +240,9 @@ lob_status lob_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
                     int32_t agent_tid, int32_t *l2_out, int32_t *agent_fills, int32_t F,
                     int32_t *agent_fill_counts, void *stream);
 
-/* Current L2 snapshot of each listed book into l2_out [n][2][levels][2]. */
+/* Current L2 snapshot of each listed book into l2_out [n][2][levels][2]: the
+ * ten-level (or l2_levels) book state the environment of Section 5.1.1 observes,
+ * in the L2 layout above. */
 lob_status lob_read_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *l2_out,
                        void *stream);
 
@@ -251,7 +265,10 @@ lob_status lob_read_status(lob_ctx *ctx, const int32_t *book_ids, int32_t n_book
  * past dump_cap, are -1 / cut off).  lob_write_book replaces each listed book's
  * orders by the dump's rows, taken in the given order up to the first row with
  * Q <= 0 or the book's capacity; the rows must be in priority order (as
- * lob_read_book writes them).  Counters and trade logs are not touched. */
+ * lob_read_book writes them: prices best first, equal prices by time), else the
+ * book is flagged LOB_BOOK_BAD_LOAD.  The book's latest time becomes at least the
+ * newest written order's, so that a later message stamped before it counts as
+ * time going backwards.  Counters and trade logs are not touched. */
 lob_status lob_read_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *out,
                          int32_t dump_cap, void *stream);
 lob_status lob_write_book(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
@@ -269,7 +286,9 @@ lob_status lob_reset(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, voi
  * not tell the orders of a level apart): order ids -9000, -9001, ... handed out
  * level by level with the ask before the bid (the column order of a LOBSTER
  * order-book row), trader id init_tid, time times[i] = (Ts, Tns) (device
- * [n_books][2], NULL = (0, 0)).  Such orders are what the cancel rule for initial
+ * [n_books][2], NULL = (0, 0)), which also becomes the book's latest time (a later
+ * message stamped before it is flagged like any time going backwards).  Such
+ * orders are what the cancel rule for initial
  * orders (id <= -9000, matched by price) acts on.  A snapshot that is not a book
  * -- prices not strictly ordered on a side, best bid >= best ask, or more levels
  * on a side than the capacity -- leaves the book empty with LOB_BOOK_BAD_LOAD. */
@@ -307,6 +326,9 @@ typedef struct {
 
 #define LOB_EXEC_TRADES_MISSING 1 /* the trade log had no room for some of a step's
                                      trades: that step's VWAP misses them          */
+#define LOB_EXEC_FILLS_MISSING 2  /* a step had more agent fills than F and the
+                                     first F did not finish the task: Q_exec, the
+                                     revenue and the reward miss the others       */
 
 typedef struct {
   int32_t tick;          /* tick size in price units                                 */
@@ -343,7 +365,11 @@ typedef struct {
  *     that order with no fused operations.  The agent's fills go to
  *     agent_fills[i] / agent_fill_counts[i] as in lob_step; state is updated.
  * W in 1..256; the trade log of a book needs room for the step's trades (2 per
- * message at most), else LOB_EXEC_TRADES_MISSING.  window [n][W][8], action_qty
+ * message at most), else LOB_EXEC_TRADES_MISSING.  A step makes at most
+ * 2 * capacity + W + 4 agent fills (each fill empties its standing order or its
+ * aggressor): with F at least that, Q_exec, the revenue and the reward count every
+ * fill; with a smaller F they are still exact when the first F fills finish the
+ * task, else the step sets LOB_EXEC_FILLS_MISSING.  window [n][W][8], action_qty
  * [n][4], state [n], obs [n][6W+8], reward [n], agent_fills [n][F][6] with F >= 1,
  * agent_fill_counts [n]; all device memory, obs 4-byte aligned. */
 lob_status lob_exec_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window,

@@ -14,7 +14,7 @@ SOURCES = [os.path.join(CSRC, "lob_kernels.hip"), os.path.join(CSRC, "lob_small.
            os.path.join(CSRC, "lob_api.cpp"), os.path.join(CSRC, "lob_serve.cpp"),
            os.path.join(CSRC, "lob_windows.cpp")]
 HEADERS = [os.path.join(CSRC, "lob_internal.h"), os.path.join(CSRC, "lob_ctx.h"),
-           os.path.join(CSRC, "lob_device.h"),
+           os.path.join(CSRC, "lob_device.h"), os.path.join(CSRC, "lob_lds_engine.h"),
            os.path.join(ROOT, "include", "lob.h")]
 ARCH = os.environ.get("LOB_OFFLOAD_ARCH", "gfx950")
 

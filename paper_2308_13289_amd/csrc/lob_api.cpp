@@ -68,8 +68,8 @@ lob_status check_list(lob_ctx *c, int32_t n) {
 }
 
 // LDS words (int2) one wave of the LDS kernel needs for a window of W slots per
-// side: 3 pair arrays per side, plus L ints of L2 scratch.
-int lds_int2_per_wave(int W, int L) { return 6 * W + (L + 1) / 2; }
+// side: 3 pair arrays per side.
+int lds_int2_per_wave(int W) { return 6 * W; }
 
 struct Geometry {
   int W;
@@ -83,7 +83,7 @@ lob_status geometry(lob_ctx *c, int window, int cap_limit, int bpb_want, Geometr
   int W = std::min(window, cap_limit);
   if (W < 1) W = 1;
   int bpb = std::max(1, std::min(16, bpb_want));
-  int per_wave = lds_int2_per_wave(W, c->L);
+  int per_wave = lds_int2_per_wave(W);
   while (bpb > 1 && (size_t)bpb * per_wave * sizeof(int2) > c->max_lds) --bpb;
   if ((size_t)per_wave * sizeof(int2) > c->max_lds) return fail(c, LOB_ECAP, "LDS window does not fit");
   g->W = W;
@@ -116,11 +116,18 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
     hipError_t e = lob::launch_process_unsorted(a, s);
     return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
   }
+  // the register kernel's forms with a tail or per-message L2 leave a book whose
+  // times go backwards to the LDS engine, launched right after them
+  auto deferred = [&](lob::ProcArgs b) -> lob_status {
+    hipError_t e = lob::launch_process_deferred(b, std::min(cap_limit, 64), s);
+    return e == hipSuccess ? LOB_OK : hip_fail(c, e, "deferred launch");
+  };
   if (c->plan.registers) {
     if (cap_limit <= lob::small_book_slots()) {  // whole books in registers
       a.bpb = std::max(1, std::min(16, bpb));
       hipError_t e = lob::launch_process_small(a, false, s);
-      return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+      if (e != hipSuccess) return hip_fail(c, e, "process launch");
+      return a.l2_mode == 1 ? deferred(a) : LOB_OK;
     }
     // the first 128 orders per side in registers, the rest in an LDS tail of
     // 16-byte entries (P, Q, OID, handle), tw per side
@@ -133,7 +140,8 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
       a.bpb = b;
       a.lds_int2_per_wave = per_wave;
       hipError_t e = lob::launch_process_small(a, true, s);
-      return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
+      if (e != hipSuccess) return hip_fail(c, e, "process launch");
+      return deferred(a);
     }
   }
   Geometry g;
@@ -307,7 +315,7 @@ lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan) {
   if (plan->layout == 1 && (size_t)lob::unsorted_lds_ints(ctx->max_cap) * sizeof(int32_t) > ctx->max_lds)
     return fail(ctx, LOB_ECAP, "layout 1: the largest book does not fit in LDS");
   for (int w : {plan->lds_slots, plan->lds_slots_big, plan->ragged_split > 0 ? plan->ragged_split : 1})
-    if ((size_t)lds_int2_per_wave(std::min(w, ctx->max_cap), ctx->L) * sizeof(int2) >
+    if ((size_t)lds_int2_per_wave(std::min(w, ctx->max_cap)) * sizeof(int2) >
         ctx->max_lds)
       return fail(ctx, LOB_ECAP, "LDS window does not fit in LDS");
   ctx->plan = *plan;

@@ -11,6 +11,7 @@
 
 namespace lob {
 hipError_t launch_process(const ProcArgs &a, bool spill, hipStream_t s);
+hipError_t launch_process_deferred(const ProcArgs &a, int W, hipStream_t s);
 hipError_t set_process_lds_limit(size_t bytes);
 hipError_t launch_reset(BookHdr *hdr, const int32_t *ids, int n, int n_total, hipStream_t s);
 hipError_t launch_status(const BookHdr *hdr, const int32_t *ids, int n, int n_total, void *out, hipStream_t s);

@@ -3,6 +3,7 @@
 // <= 128 wholly in registers).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include "lob_internal.h"
@@ -44,6 +45,24 @@ __device__ __forceinline__ int scan_incl(int x) {
   return x;
 }
 
+// The same scan of non-negative values with saturating adds: lane l receives
+// min(x_0 + ... + x_l, INT_MAX) exactly, whatever the sum.
+__device__ __forceinline__ int sat_add(int a, int b) { return __builtin_elementwise_add_sat(a, b); }
+__device__ __forceinline__ int scan_incl_sat(int x) {
+  x = sat_add(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true));
+  x = sat_add(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true));
+  x = sat_add(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true));
+  x = sat_add(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true));
+  x = sat_add(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+  x = sat_add(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
+  return x;
+}
+
+// Quantities below this bound take the matching scan's exact int32 form: each
+// resting quantity clamped to q + 1 decides every fill test as the true value does,
+// and 64 such values sum below 2^31.
+constexpr int kScanExactQ = 1 << 24;
+
 // Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane l receives
 // lane l-1 (shr) or l+1 (shl); the lane with no source (0, resp. 63) receives `fill`.
 __device__ __forceinline__ int shr1(int x, int fill) {
@@ -54,6 +73,38 @@ __device__ __forceinline__ int shl1(int x, int fill) {
 }
 // Value of x in lane `src` (0..63) for every lane.
 __device__ __forceinline__ int from_lane(int x, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, x); }
+
+// L2 level quantities over one 64-slot chunk of a side taken in priority order.  q:
+// the slot's quantity (0 past the side's end); ml: ballot of the slots that end a
+// level.  A level's quantity is summed exactly and reported as min(sum, INT_MAX)
+// (the L2 record is int32).  Returns that quantity on the lanes of ml; carry (uniform)
+// is the exact quantity of the level left open by the chunks before and becomes the
+// one left open after this chunk.  Quantities below 2^25 sum in one int32 scan; a
+// chunk holding a larger one sums its 16-bit halves separately.
+__device__ __forceinline__ int level_qty(int q, uint64_t ml, long long &carry) {
+  const uint64_t below = ml & mask_lt();
+  const int src = below ? 63 - __builtin_clzll(below) : 0;
+  const int last = ml ? 63 - __builtin_clzll(ml) : 0;
+  int res;
+  if (__builtin_expect(ballot(q >= (1 << 25)) == 0, 1)) {
+    const int loc = scan_incl(q);
+    const int prev = from_lane(loc, src);
+    const int cc = carry > INT_MAX ? INT_MAX : (int)carry;
+    res = below ? loc - prev : sat_add(cc, loc);
+    const int tot = rdlane(loc, 63);
+    carry = ml ? (long long)(tot - rdlane(loc, last)) : carry + tot;
+  } else {
+    const int lo = scan_incl(q & 0xffff), hi = scan_incl((int)((unsigned)q >> 16));
+    const long long loc = ((long long)hi << 16) + lo;
+    const long long prev = ((long long)from_lane(hi, src) << 16) + from_lane(lo, src);
+    const long long v = below ? loc - prev : carry + loc;
+    res = v > INT_MAX ? INT_MAX : (int)v;
+    const long long tot = ((long long)rdlane(hi, 63) << 16) + rdlane(lo, 63);
+    const long long at_last = ((long long)rdlane(hi, last) << 16) + rdlane(lo, last);
+    carry = ml ? tot - at_last : carry + tot;
+  }
+  return res;
+}
 
 // Wave-uniform state of the book being processed.
 struct State {

@@ -169,6 +169,9 @@ __global__ void __launch_bounds__(256) k_exec_finish(BookHdr *hdr, const int32_t
     B += take;
     exec += take;
   }
+  // fills past the buffer count only if the stored ones left the task unfinished
+  int flags = s.flags;
+  if (fill_counts[i] > F && exec < s.task_qty) flags |= LOB_EXEC_FILLS_MISSING;
   double R = 0.0;
   if (sq > 0) {
     const double vwap = (double)sqp / (double)sq;
@@ -195,7 +198,8 @@ __global__ void __launch_bounds__(256) k_exec_finish(BookHdr *hdr, const int32_t
   state[i].revenue = s.revenue + A;
   state[i].done = (exec >= s.task_qty || t.x >= s.end_s) ? 1 : 0;
   // trades of the step that found no room in the log
-  if (h->n_trades - aux[2 * i + 1] > after - before) state[i].flags = s.flags | LOB_EXEC_TRADES_MISSING;
+  if (h->n_trades - aux[2 * i + 1] > after - before) flags |= LOB_EXEC_TRADES_MISSING;
+  state[i].flags = flags;
   if (!p.keep_trades && log) h->log_count = before;
 }
 

@@ -40,7 +40,8 @@ struct alignas(16) BookHdr {
       rejected_qty, cancel_miss;
   int32_t last_ts, last_tns;  // time of the last processed message
   int32_t seen_time;          // 1 once a message with a valid type was processed
-  int32_t pad[3];
+  int32_t deferred;           // 1: left by the register kernel to k_process_deferred
+  int32_t pad[2];
 };
 static_assert(sizeof(BookHdr) == 144, "BookHdr layout");
 

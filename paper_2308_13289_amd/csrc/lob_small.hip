@@ -165,6 +165,15 @@ struct RState {
 template <bool TAIL, int X>
 constexpr bool kAgentMask = !TAIL && (X & 2) == 0;
 
+// Books whose times go backwards (Section 4.1: among equal prices the earlier time
+// has priority, which then differs from arrival order).  Without a tail and without
+// per-message L2, the kernel carries a second copy of its message loop whose insert
+// compares times (kTimedInline); the other forms leave such a book uncommitted and
+// mark it for the LDS engine, launched after them (k_process_deferred), which keeps
+// each order's time beside it.  Either way the hot loop holds no code for it.
+template <bool TAIL, int X>
+constexpr bool kTimedInline = !TAIL && (X & 2) == 0;
+
 template <bool TAIL, int X>
 __device__ __forceinline__ bool agent_msg(const RState &st, const int4 &v, int j) {
   if constexpr (kAgentMask<TAIL, X>)
@@ -499,15 +508,24 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
       const uint64_t mc = ballot(valid) & ballot(at);
       const bool cross = valid & at;
       const int qv = cross ? F.q : 0;
-      const int incl = scan_incl(qv);
-      const int excl = incl - qv;
+      // running sums of the crossing quantities; excl is exact wherever it is below q
+      int incl, excl;
+      if (LOB_LIKELY(q < kScanExactQ)) {
+        const int qc = min(qv, q + 1);
+        incl = scan_incl(qc);
+        excl = incl - qc;
+      } else {
+        incl = scan_incl_sat(qv);
+        excl = shr1(incl, 0);
+      }
       const bool takes = cross & (excl < q);
       const uint64_t mt = mc & ballot(excl < q);
       if (mt == 0) break;
       const int ntr = popc(mt);
-      const bool full = cross & (incl <= q);
-      const int nfull = popc(mc & ballot(incl <= q));
-      const int fill = takes ? min(qv, q - excl) : 0;
+      const int room = q - excl;
+      const bool full = takes & (qv <= room);
+      const int nfull = popc(ballot(full));
+      const int fill = takes ? min(qv, room) : 0;
       stage_many<TAIL, X>(st, sg, ntr, F.p, fill, F.o, j, (F.h & 1) != 0, v);
       F.q = (takes & !full) ? F.q - fill : F.q;  // the partially filled order, if any
       const int consumed = (nfull == ntr) ? rdlane(incl, ntr - 1) : q;
@@ -525,16 +543,84 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
   return q;
 }
 
-// Add (Section 4.1, item 1) on side SD: the new order goes behind every order with
-// an equal or better price, i.e. at its price-time position.
-// hnd: the new order's handle.
-template <int SD, bool TAIL>
-__device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int oid, int hnd) {
+// Where the stream of the book being processed lives (for the handles' records).
+struct Streams {
+  const int32_t *msgs, *msgs2;
+  long long beg1, n1, beg2, total;
+};
+
+// Where every order's time is kept: the records of this launch's stream for orders
+// it added, the loaded book (the buffer this launch does not write) for the others.
+struct Origin {
+  Streams m;
+  const int2 *hb;  // the loaded book, both sides
+  int cap;
+};
+
+// The message loop carries the addresses of those times packed into the lanes of
+// one VGPR (lane k holds 32-bit word k), read back with ds_bpermute into VGPRs only on
+// the rare path that needs them: held in scalar registers they would raise the
+// kernel's register count, and its occupancy, for a path that almost never runs.
+// Words 0-1: record 0 of source 1; 2-3: where record k of source 2 sits for k >= n1;
+// 4: n1; 5-6 and 7-8: the (Ts, Tns) arrays of the loaded ask and bid sides.
+__device__ __forceinline__ int pack_origin(const Origin &g) {
+  const uint64_t b1 = (uint64_t)(uintptr_t)g.m.msgs + (uint64_t)g.m.beg1 * (kMsgFields * 4);
+  const uint64_t b2 = (uint64_t)(uintptr_t)g.m.msgs2 + (uint64_t)(g.m.beg2 - g.m.n1) * (kMsgFields * 4);
+  const uint64_t t0 = (uint64_t)(uintptr_t)(g.hb + 2 * (int64_t)g.cap);
+  const uint64_t t1 = (uint64_t)(uintptr_t)(g.hb + 5 * (int64_t)g.cap);
+  const uint32_t w[9] = {(uint32_t)b1, (uint32_t)(b1 >> 32), (uint32_t)b2, (uint32_t)(b2 >> 32), (uint32_t)g.m.n1,
+                         (uint32_t)t0, (uint32_t)(t0 >> 32), (uint32_t)t1, (uint32_t)(t1 >> 32)};
+  int pk = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) pk = wl(pk, (int)w[k], k);
+  asm volatile("" : "+v"(pk));  // opaque: the words are read back from the lanes
+  return pk;
+}
+
+// Address of the (Ts, Tns) of the order with handle h on side sd, one per lane.  Must
+// run with every lane of the wave active: a ds_bpermute reads zero from an inactive
+// source lane.  h may be anything; the address is valid only where an order is held.
+__device__ __forceinline__ const int2 *time_addr(int h, int pk, int sd) {
+  const int idx = h >> 1;
+  const int n1 = from_lane(pk, 4);
+  const int w = idx >= 0 ? (idx < n1 ? 0 : 2) : 5 + 2 * sd;
+  const uint64_t base = (uint64_t)(uint32_t)from_lane(pk, w) | (uint64_t)(uint32_t)from_lane(pk, w + 1) << 32;
+  const uint64_t off = idx >= 0 ? (uint64_t)idx * (kMsgFields * 4) + 24 : (uint64_t)(-1 - idx) * 8;
+  return reinterpret_cast<const int2 *>(base + off);
+}
+
+// Whether each held order (p, handle h; held: this lane holds an order) is ahead of
+// a new order (P, ts, tns) on side SD under price-time priority: a better price, or
+// the same price and a time at or before (ts, tns) (equal times: the standing order
+// arrived first).  For books whose times went backwards; otherwise every standing
+// order is at most as old as the new one and an equal price alone puts it ahead.
+// Every lane of the wave active (time_addr).
+template <int SD>
+__device__ __forceinline__ bool ahead_timed(bool held, int p, int h, int P, int ts, int tns, int pk) {
+  const int2 *ta = time_addr(h, pk, SD);
+  bool ahead = held & (SD == 1 ? p > P : p < P);
+  if (held & (p == P)) {
+    const int2 t = *ta;
+    ahead = (t.x < ts) | ((t.x == ts) & (t.y <= tns));
+  }
+  return ahead;
+}
+
+// Add (Section 4.1, item 1) on side SD: the new order goes to its price-time
+// position.  While a book's times have never gone backwards every standing order is
+// at most as old as the new one, so that position is behind every order with an
+// equal or better price; in a book flagged for times going backwards (TIMED) the
+// times of the orders at the new order's price are compared too (ahead_timed).
+// hnd: the new order's handle; it is message j of the chunk v = (OID, TID, Ts, Tns).
+template <int SD, bool TAIL, bool TIMED>
+__device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int oid, int hnd, const int4 &v_,
+                                       int j, int pk) {
+  static_assert(!(TAIL && TIMED), "the TAIL form leaves such books to the LDS engine");
   Side &S = side<SD>(bk);
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
   const int n = st.n[SD];
-  if constexpr (!TAIL) {
+  if constexpr (!TAIL && !TIMED) {
     // without a tail a side rarely holds 64 orders: then only chunk 0 takes part,
     // and one test covers the capacity too
     if (LOB_LIKELY(n < st.small_lim)) {
@@ -556,12 +642,21 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
     return;
   }
   const int nr = n < kSlots ? n : kSlots;
-  // the orders ahead (price equal or better) form a prefix, so chunk 1 holds some
-  // only when chunk 0 is all ahead: both counts add up without a test (without a
-  // tail chunk 1 is rarely in use and is skipped while it is empty)
-  int pos = popc(lt_mask(l, nr) & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
-  if (TAIL || LOB_UNLIKELY(nr > kWave))
-    pos += popc(lt_mask(l + kWave, nr) & (SD == 1 ? ge_mask(S.c1.p, P) : le_mask(S.c1.p, P)));
+  // the orders ahead form a prefix, so chunk 1 holds some only when chunk 0 is all
+  // ahead: both counts add up without a test (without a tail chunk 1 is rarely in
+  // use and is skipped while it is empty)
+  int ts = 0, tns = 0;
+  int pos;
+  if constexpr (TIMED) {
+    ts = rdlane(v_.z, j);
+    tns = rdlane(v_.w, j);
+    pos = popc(ballot(ahead_timed<SD>(l < nr, S.c0.p, S.c0.h, P, ts, tns, pk)));
+    if (nr > kWave) pos += popc(ballot(ahead_timed<SD>(l + kWave < nr, S.c1.p, S.c1.h, P, ts, tns, pk)));
+  } else {
+    pos = popc(lt_mask(l, nr) & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
+    if (TAIL || LOB_UNLIKELY(nr > kWave))
+      pos += popc(lt_mask(l + kWave, nr) & (SD == 1 ? ge_mask(S.c1.p, P) : le_mask(S.c1.p, P)));
+  }
   Chunk v;
   v.p = P;
   v.q = Q;
@@ -713,14 +808,15 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
 
 // L2 of one side: the first L distinct prices with their summed quantities into
 // out[0..L) as (price, qty); missing levels (-1, 0).  A level is a run of equal
-// prices in priority order; its quantity is the running sum at its last order minus
-// the running sum at the previous level's last order.  The slots are taken 64 at a
-// time in priority order: the two register chunks, then (TAIL form) the tail.
+// prices in priority order; its quantity is the exact sum of the run, capped at
+// INT_MAX (level_qty).  The slots are taken 64 at a time in priority order: the two
+// register chunks, then (TAIL form) the tail.
 template <bool TAIL>
 __device__ __forceinline__ void l2_side(const Side &S, const Tail &tl, int n, int L, int2 *out) {
   const int l = lane_id();
   const int nr = n < kSlots ? n : kSlots;
-  int levels = 0, q_before = 0, end_before = 0;
+  int levels = 0;
+  long long carry = 0;
   const int nchunks = TAIL ? (n + kWave - 1) / kWave : 2;
   for (int c = 0; c < nchunks && levels < L; ++c) {
     if (c * kWave >= n) break;
@@ -744,16 +840,11 @@ __device__ __forceinline__ void l2_side(const Side &S, const Tail &tl, int n, in
       next = (s + 1 < n) ? tl.a[n - 2 - s].x : 0;
     }
     const bool is_last = valid & ((s + 1 == n) | (next != p));
-    const int incl = q_before + scan_incl(valid ? q : 0);
     const uint64_t ml = ballot(is_last);
-    const uint64_t below = ml & mask_lt();
-    const int src = below ? 63 - __builtin_clzll(below) : 0;
-    const int prev_end = from_lane(incl, src);
-    const int lev = levels + popc(below);
-    if (is_last && lev < L) out[lev] = make_int2(p, incl - (below ? prev_end : end_before));
-    if (ml) end_before = rdlane(incl, 63 - __builtin_clzll(ml));
+    const int lq = level_qty(valid ? q : 0, ml, carry);
+    const int lev = levels + popc(ml & mask_lt());
+    if (is_last && lev < L) out[lev] = make_int2(p, lq);
     levels += popc(ml);
-    q_before = rdlane(incl, 63);
   }
   const int have = levels < L ? levels : L;
   if (l >= have && l < L) out[l] = make_int2(-1, 0);
@@ -784,19 +875,19 @@ __device__ __forceinline__ int handle(const RState &st, int k, const int4 &v, in
 // Message j of the chunk held as u = (type, side, P, Q), v = (oid, tid, ts, tns)
 // across the lanes, message k of the book's stream; each case reads only the
 // fields it uses.
-template <bool TAIL, int X>
+template <bool TAIL, int X, bool TIMED>
 __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int code, const int4 &u, const int4 &v,
-                                            int j, int k) {
+                                            int j, int k, int pk) {
   // tested in order of frequency: limit orders, cancels, market orders
   if (LOB_LIKELY(code < 2)) {
     const int P = rdlane(u.z, j), Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 7
     if (code == 0) {
       const int rem = match<1, TAIL, X, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<0, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j));
+      if (rem > 0) insert<0, TAIL, TIMED>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j), v, j, pk);
     } else {
       const int rem = match<0, TAIL, X, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<1, TAIL>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j));
+      if (rem > 0) insert<1, TAIL, TIMED>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j), v, j, pk);
     }
   } else if (code < 4) {
     if (code == 2)
@@ -845,11 +936,13 @@ __device__ __forceinline__ void fetch_chunk(const ProcArgs &a, long long beg1, l
 }
 
 // The book's messages in 64-message chunks, each loaded one chunk ahead of its use;
-// (un, vn) is the first chunk, already requested by the caller.
+// (un, vn) is the first chunk, already requested by the caller.  Returns true, with
+// the book's state abandoned, when a chunk shows the times going backwards in a form
+// without the timed loop (kTimedInline).
 template <bool TAIL, int X>
-__device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, const ProcArgs &a, long long beg1,
+__device__ __forceinline__ bool process_all(Book &bk, RState &st, Stage &sg, const ProcArgs &a, long long beg1,
                                             long long n1, long long beg2, long long n2, int32_t *l2_rows, int4 un,
-                                            int4 vn, int rank) {
+                                            int4 vn, int rank, int pk) {
   const int l = lane_id();
   const long long total = n1 + n2;
 #pragma nounroll
@@ -886,16 +979,28 @@ __device__ __forceinline__ void process_all(Book &bk, RState &st, Stage &sg, con
     if constexpr ((X & 1) != 0 && kAgentMask<TAIL, X>) st.agm = ballot(v.y == st.agent_tid);
     // messages of this chunk that come from source 1 (they get per-message L2 rows)
     const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
+    if (LOB_LIKELY(!(st.flags & kFlagTimeOrder))) {
 #pragma nounroll
-    for (int j = 0; j < cnt; ++j) {
-      const int c = rdlane(code, j);
-      process_msg<TAIL, X>(bk, st, sg, c, u, v, j, (int)k0 + j);
-      if constexpr ((X & 2) != 0) {
-        if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+      for (int j = 0; j < cnt; ++j) {
+        const int c = rdlane(code, j);
+        process_msg<TAIL, X, false>(bk, st, sg, c, u, v, j, (int)k0 + j, pk);
+        if constexpr ((X & 2) != 0) {
+          if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+        }
       }
+    } else if constexpr (kTimedInline<TAIL, X>) {
+      // a book whose times went backwards: the same loop with the timed insert
+#pragma nounroll
+      for (int j = 0; j < cnt; ++j) {
+        const int c = rdlane(code, j);
+        process_msg<TAIL, X, true>(bk, st, sg, c, u, v, j, (int)k0 + j, pk);
+      }
+    } else {
+      return true;
     }
     flush<TAIL, X>(st, sg, v);  // the staged records name messages of this chunk
   }
+  return false;
 }
 
 // Slot s (< n) of one side of the loaded book: its P, Q, OID and handle.
@@ -933,11 +1038,6 @@ __device__ __forceinline__ void load_chunk(Chunk &x, const int2 *base, int cap, 
   }
 }
 
-// Where the stream of the book being processed lives (for the handles' records).
-struct Streams {
-  const int32_t *msgs, *msgs2;
-  long long beg1, n1, beg2, total;
-};
 
 // TID, Ts, Tns of order x (one per lane), found through its handle in the stream
 // or in the loaded side `src` (the other buffer, not written by this launch).
@@ -995,6 +1095,12 @@ __device__ __forceinline__ void put_order(const Chunk &x, const int4 &mt, int2 *
   dst[2 * cap + s] = make_int2(mt.y, mt.z);
 }
 
+// The book goes to the LDS engine after this launch (kTimedInline): it is marked in
+// its header; nothing of this launch's work on it is committed.
+__device__ __forceinline__ void defer_book(BookHdr *h) {
+  if (lane_id() == 0) h->deferred = 1;
+}
+
 // TAIL form: tails of the two sides in LDS at `lds`, a.W entries each.
 template <bool TAIL, int X>
 __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
@@ -1031,12 +1137,18 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   st.n[0] = uni(h->n[0]);
   st.n[1] = uni(h->n[1]);
   st.cap = uni(h->cap);
-  st.small_lim = st.cap < kWave ? st.cap : kWave;
   if (st.cap > (TAIL ? kSlots + a.W : kSlots)) {  // not launched for such books; leave the book untouched
     if (l == 0) h->flags |= kFlagBadLoad;
     return;
   }
   st.flags = uni(h->flags);
+  if constexpr (!kTimedInline<TAIL, X>) {
+    if (LOB_UNLIKELY(st.flags & kFlagTimeOrder)) {
+      defer_book(h);
+      return;
+    }
+  }
+  st.small_lim = st.cap < kWave ? st.cap : kWave;
   st.trades = st.misses = 0;
   st.cancelled_qty = st.market_discarded = st.rejected_qty = 0;
   st.last_ts = uni(h->last_ts);
@@ -1098,17 +1210,28 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   // int32 apart per listed book
   int32_t *l2_rows = a.l2_mode != 1 ? nullptr
                      : a.l2_stride ? a.l2_out + (int64_t)i * a.l2_stride : a.l2_out + beg1 * 4 * a.levels;
+  Origin g;
+  g.m.msgs = a.msgs;
+  g.m.msgs2 = a.msgs2;
+  g.m.beg1 = beg1;
+  g.m.n1 = n1;
+  g.m.beg2 = (long long)i * a.w2;
+  g.m.total = n1 + n2;
+  g.hb = hb;
+  g.cap = cap;
   if constexpr (TAIL) fetch_chunk(a, beg1, n1, (long long)i * a.w2, n1 + n2, 0, u0, v0);
-  process_all<TAIL, X>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows, u0, v0, rank);
+  const bool went_back =
+      process_all<TAIL, X>(bk, st, sg, a, beg1, n1, (long long)i * a.w2, n2, l2_rows, u0, v0, rank,
+                           kTimedInline<TAIL, X> ? pack_origin(g) : 0);
+  if (LOB_UNLIKELY(went_back)) {
+    // nothing is committed yet: the header, and the buffer the book was loaded from,
+    // are as they were, so the LDS engine takes this launch's stream from the start
+    defer_book(h);
+    return;
+  }
   if (a.l2_mode == 2) write_l2<TAIL>(bk, st, a.levels, a.l2_out + (int64_t)row * 4 * a.levels);
 
-  Streams ms;
-  ms.msgs = a.msgs;
-  ms.msgs2 = a.msgs2;
-  ms.beg1 = beg1;
-  ms.n1 = n1;
-  ms.beg2 = (long long)i * a.w2;
-  ms.total = n1 + n2;
+  const Streams &ms = g.m;
   if constexpr (!TAIL) {
     // the orders' TID, Ts, Tns are all requested before any order is written (the
     // written buffer may alias the read ones as far as the compiler knows)

@@ -8,8 +8,8 @@
 // wavefront per book, both sides in LDS as unsorted arrays, each search a
 // wave-wide reduction -- so that the sorted layout of lob_kernels.hip and
 // lob_small.hip can be measured against it on the same inputs.  Results are
-// identical to theirs: priority among equal prices is arrival order, and the book
-// goes back to HBM in priority order.
+// identical to theirs: priority among equal prices is the earlier (Ts, Tns), then
+// arrival order, and the book goes back to HBM in priority order.
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <stdint.h>
@@ -34,10 +34,25 @@ __device__ __forceinline__ USide side_at(int *base, int cap, int sd) {
   return {b, b + cap, b + 2 * cap, b + 3 * cap, b + 4 * cap, b + 5 * cap, b + 6 * cap};
 }
 
-// Is (p, a) ahead of (q, b) on side SD?  Better price, then earlier arrival.
+// Priority key of an order: price, time and arrival rank.
+struct Key {
+  int p, ts, tns, a;
+};
+
+__device__ __forceinline__ Key key_at(const USide &S, int s) { return {S.P[s], S.TS[s], S.TNS[s], S.AR[s]}; }
+
+// Is x ahead of y on side SD?  Better price, then earlier time, then earlier arrival.
 template <int SD>
-__device__ __forceinline__ bool ahead(int p, int a, int q, int b) {
-  return (SD == 1 ? p > q : p < q) || (p == q && a < b);
+__device__ __forceinline__ bool ahead(const Key &x, const Key &y) {
+  if (x.p != y.p) return SD == 1 ? x.p > y.p : x.p < y.p;
+  if (x.ts != y.ts) return x.ts < y.ts;
+  if (x.tns != y.tns) return x.tns < y.tns;
+  return x.a < y.a;
+}
+
+__device__ __forceinline__ Key shfl_key(const Key &k, int o) {
+  return {__shfl_xor(k.p, o, kWave), __shfl_xor(k.ts, o, kWave), __shfl_xor(k.tns, o, kWave),
+          __shfl_xor(k.a, o, kWave)};
 }
 
 // The best live position of side SD among those with pred(s), -1 if none: a scan of
@@ -45,23 +60,23 @@ __device__ __forceinline__ bool ahead(int p, int a, int q, int b) {
 template <int SD, typename Pred>
 __device__ __forceinline__ int best_slot(const USide &S, int cap, Pred pred) {
   const int l = lane_id();
-  int bp = 0, ba = INT_MAX, bs = -1;
+  Key bk = {0, 0, 0, INT_MAX};
+  int bs = -1;
   for (int s = l; s < cap; s += kWave) {
     const int q = S.Q[s];
     if (q > 0 && pred(s)) {
-      const int p = S.P[s], a = S.AR[s];
-      if (bs < 0 || ahead<SD>(p, a, bp, ba)) {
-        bp = p;
-        ba = a;
+      const Key k = key_at(S, s);
+      if (bs < 0 || ahead<SD>(k, bk)) {
+        bk = k;
         bs = s;
       }
     }
   }
   for (int o = 32; o >= 1; o >>= 1) {
-    const int op = __shfl_xor(bp, o, kWave), oa = __shfl_xor(ba, o, kWave), os = __shfl_xor(bs, o, kWave);
-    if (os >= 0 && (bs < 0 || ahead<SD>(op, oa, bp, ba))) {
-      bp = op;
-      ba = oa;
+    const Key ok = shfl_key(bk, o);
+    const int os = __shfl_xor(bs, o, kWave);
+    if (os >= 0 && (bs < 0 || ahead<SD>(ok, bk))) {
+      bk = ok;
       bs = os;
     }
   }
@@ -177,11 +192,13 @@ __device__ __forceinline__ void l2_side(const UBook &bk, int L, int2 *out) {
       continue;
     }
     px = uni(px);
-    int qs = 0;
+    // the level's exact sum (64-bit), reported capped at INT_MAX
+    long long qs = 0;
     for (int s = l; s < bk.cap; s += kWave)
       if (S.Q[s] > 0 && S.P[s] == px) qs += S.Q[s];
-    for (int o = 32; o >= 1; o >>= 1) qs += __shfl_xor(qs, o, kWave);
-    if (l == 0) out[lev] = make_int2(px, qs);
+    for (int o = 32; o >= 1; o >>= 1)
+      qs += ((long long)__shfl_xor((int)(qs >> 32), o, kWave) << 32) | (unsigned)__shfl_xor((int)(unsigned)qs, o, kWave);
+    if (l == 0) out[lev] = make_int2(px, qs > INT_MAX ? INT_MAX : (int)qs);
     prev = px;
     have_prev = true;
   }
@@ -339,12 +356,13 @@ __device__ void run_book(const ProcArgs &a, int i, int *lds) {
     for (int s = l; s < st.cap; s += kWave) {
       const int q = S.Q[s];
       if (q <= 0) continue;
-      const int p = S.P[s], ar = S.AR[s];
+      const Key me = key_at(S, s);
       int r = 0;
       for (int t = 0; t < st.cap; ++t) {
         if (S.Q[t] <= 0) continue;
-        r += sd == 1 ? ahead<1>(S.P[t], S.AR[t], p, ar) : ahead<0>(S.P[t], S.AR[t], p, ar);
+        r += sd == 1 ? ahead<1>(key_at(S, t), me) : ahead<0>(key_at(S, t), me);
       }
+      const int p = me.p;
       hb[(int64_t)(sd * 3 + 0) * st.cap + r] = make_int2(p, q);
       hb[(int64_t)(sd * 3 + 1) * st.cap + r] = make_int2(S.O[s], S.T[s]);
       hb[(int64_t)(sd * 3 + 2) * st.cap + r] = make_int2(S.TS[s], S.TNS[s]);

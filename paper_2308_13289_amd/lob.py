@@ -33,6 +33,7 @@ EXEC_STATE_DTYPE = np.dtype([("task_side", np.int32), ("task_qty", np.int32), ("
                              ("next_oid", np.int32), ("flags", np.int32)])
 assert EXEC_STATE_DTYPE.itemsize == 48
 EXEC_TRADES_MISSING = 1
+EXEC_FILLS_MISSING = 2
 
 
 class ExecParams(ctypes.Structure):

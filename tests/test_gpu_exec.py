@@ -85,3 +85,83 @@ def test_exec_steps_match_oracle(res):
             np.testing.assert_array_equal(dump[i, sd, :len(want)], want)
     # the steps' trades left the log (keep_trades off)
     assert (ctx.read_status()["log_records"] == 0).all()
+
+
+
+@pytest.mark.parametrize("res", [{"registers": 1}, {"registers": 0}, {"layout": 1}])
+@pytest.mark.parametrize("F", [8, 2 * 100 + 50 + 4])
+def test_exec_step_more_fills_than_buffer(res, F):
+    """Step 1 rests an agent order of 1000 at the mid price, inside the spread; step 2's
+    50 data market orders of 1 share each all fill against it: 50 agent fills.  With F
+    at the bound of lob.h (2 * capacity + W + 4) every result equals the oracle's;
+    with F = 8 a task of 5 shares, finished by the first 5 fills, is still exact, and
+    a task the first 8 fills leave unfinished is flagged LOB_EXEC_FILLS_MISSING with
+    Q_exec and the revenue of those 8 fills."""
+    n_books, cap, Wn = 8, 100, 50
+    w = W.uniform(n_books, 1, cap=cap, tag=31)
+    seeds = 2 * (cap // 2)
+    seed_msgs = w.msgs.reshape(n_books, seeds + 1, 8)[:, :seeds]
+    ctx = lob.Context(w.caps, l2_levels=10, trade_log_records=np.full(n_books, 2 * (Wn + 4) + 2 * cap))
+    ctx.set_plan(**res)
+    ctx.process(to_dev(seed_msgs.reshape(-1, 8)), to_dev(np.arange(n_books + 1, dtype=np.int64) * seeds))
+    state = np.zeros(n_books, lob.EXEC_STATE_DTYPE)
+    envs = []
+    win1 = np.zeros((n_books, Wn, 8), np.int32)
+    win2 = np.zeros((n_books, Wn, 8), np.int32)
+    for i in range(n_books):
+        b = O.Book(cap)
+        for m in seed_msgs[i]:
+            b.process(m)
+        ask, bid = b.dump(0)[0, 0], b.dump(1)[0, 0]
+        s = state[i]
+        side = 1 if i % 2 else -1
+        s["task_side"] = side
+        s["task_qty"] = 1_000_000_000 if i % 4 < 2 else 5
+        s["p_init"] = (int(ask) + int(bid)) // 2
+        s["start_s"], s["start_ns"] = 34200, 0
+        s["end_s"] = 40000
+        s["next_oid"] = 1_000_000
+        # step 1: one cancel that finds nothing (it sets the step's time); step 2:
+        # market orders of 1 share against the agent's side
+        win1[i, 0] = [2, 1, 1, 1, 999_999, 7, 34200, 0]
+        for k in range(Wn):
+            win2[i, k] = [4, -side, 0, 1, 2000 + k, 7, 34200, 1 + k]
+        envs.append(ExecEnv(b, side, s["task_qty"], s["p_init"], (34200, 0), s["end_s"], s["next_oid"], tick=100,
+                            passive_ticks=2, agent_tid=AGENT, lam=0.3))
+    d_state = torch.from_numpy(state.view(np.uint8)).cuda()
+    obs = torch.zeros((n_books, 6 * Wn + 8), dtype=torch.int32, device="cuda:0")
+    reward = torch.zeros(n_books, dtype=torch.float64, device="cuda:0")
+    fills = torch.zeros((n_books, F, 6), dtype=torch.int32, device="cuda:0")
+    counts = torch.zeros(n_books, dtype=torch.int32, device="cuda:0")
+    acts = [np.tile(np.array([0, 1000, 0, 0], np.int32), (n_books, 1)), np.zeros((n_books, 4), np.int32)]
+    flagged = 0
+    for step, (win, act) in enumerate(zip([win1, win2], acts)):
+        ctx.exec_step(to_dev(win), to_dev(act), d_state, obs, reward, fills, counts, tick=100, passive_ticks=2,
+                      agent_tid=AGENT, lam=0.3)
+        g_state = d_state.cpu().numpy().view(lob.EXEC_STATE_DTYPE)
+        g_counts, g_fills, g_obs, g_rew = counts.cpu().numpy(), fills.cpu().numpy(), obs.cpu().numpy(), \
+            reward.cpu().numpy()
+        for i, env in enumerate(envs):
+            before = env.exec_qty
+            o_obs, o_rew, o_fills = env.step(win[i], act[i])
+            assert g_counts[i] == len(o_fills), (step, i)
+            assert step == 0 or len(o_fills) == Wn, (i, len(o_fills))
+            np.testing.assert_array_equal(g_fills[i, :min(F, len(o_fills))], o_fills[:F])
+            np.testing.assert_array_equal(g_obs[i, :-1], o_obs[:-1])  # the last entry is Q_exec
+            gs = g_state[i]
+            # Q_exec and revenue over the first F fills, capped at the task size
+            first, rev = before, 0
+            for f in o_fills[:F]:
+                take = min(int(f[1]), env.task_qty - first)
+                if take > 0:
+                    first += take
+                    rev += take * int(f[0])
+            if len(o_fills) > F and first < env.task_qty:
+                flagged += 1
+                assert gs["flags"] == lob.EXEC_FILLS_MISSING, (step, i)
+                assert (gs["exec_qty"], gs["revenue"]) == (first, rev), (step, i)
+            else:
+                assert gs["flags"] == 0, (step, i)
+                assert (gs["exec_qty"], gs["revenue"], gs["done"]) == (env.exec_qty, env.revenue, env.done), i
+                assert g_obs[i, -1] == o_obs[-1] and g_rew[i] == o_rew, (step, i)
+    assert flagged == (n_books // 2 if F == 8 else 0)

@@ -47,15 +47,19 @@ def test_selftest_primitives():
     np.testing.assert_array_equal(out[512:576], np.where(lanes == 17, -9, x))
 
 
-RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}, "unsorted": {"layout": 1}}
+RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}, "unsorted": {"layout": 1},
+             "tail": {"registers": 1}}
 
 
-@pytest.mark.parametrize("res", ["regs", "lds"])
+@pytest.mark.parametrize("res", ["regs", "lds", "unsorted", "tail"])
 def test_golden_cases_on_gpu(res):
+    """The hand-worked cases; "tail" adds a book of capacity 300 to the call, which
+    puts the register kernel in its TAIL form for every book."""
     cases = all_cases()
-    caps = np.array([c.cap for c in cases], np.int32)
+    caps = np.array([c.cap for c in cases] + ([300] if res == "tail" else []), np.int32)
     msgs = np.concatenate([c.msgs for c in cases])
-    offs = np.concatenate([[0], np.cumsum([len(c.msgs) for c in cases])]).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum([len(c.msgs) for c in cases])] +
+                          ([[len(msgs)]] if res == "tail" else [])).astype(np.int64)
     g = run_gpu(caps, msgs, offs, levels=3, l2_mode=lob.L2_FINAL, plan=RESIDENCY[res])
     for i, c in enumerate(cases):
         tr = g["trades"][g["trade_offs"][i]:g["trade_offs"][i + 1]]

@@ -216,3 +216,26 @@ def test_step_sweeps_store_fills_mid_chunk(cap):
     ol2, ofills = oracle_steps(caps, seed_blk, windows, actions)
     assert min(len(ofills[0][b]) for b in range(n)) > 25  # agent fills on both sides of the sweep
     check_against_oracle(l2, fills, counts, ol2, ofills, F)
+
+
+@pytest.mark.parametrize("cap", [100, 300], ids=["registers", "tail"])
+def test_step_times_out_of_order(cap):
+    """In half the books some windows carry their time stamps in reverse order, so
+    that from then on times go backwards: among equal prices the earlier time still
+    wins (Section 4.1).  Capacity 100 runs the register kernel's timed loop; 300
+    hands such books to the LDS engine after each step's launch."""
+    w, seed_blk, windows, actions = step_case(32, 12, cap=cap)
+    windows = windows.copy()
+    for b in range(0, 32, 2):
+        for s in range(b % 3, 12, 3):
+            windows[b, s, :, 6:8] = windows[b, s, ::-1, 6:8]
+    F = 64
+    R = StepRunner(w.caps, seed_blk, windows, actions, F=F)
+    R.seed()
+    R.run_steps()
+    l2, fills, counts = R.outputs()
+    ol2, ofills = oracle_steps(w.caps, seed_blk, windows, actions)
+    check_against_oracle(l2, fills, counts, ol2, ofills, F)
+    st = R.ctx.read_status()
+    flagged = (st["flags"] & lob.BOOK_TIME_ORDER) != 0
+    assert flagged[::2].all() and not flagged[1::2].any()
