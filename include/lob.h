@@ -377,6 +377,20 @@ lob_status lob_exec_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
                          lob_exec_state *state, int32_t *obs, double *reward, int32_t *agent_fills, int32_t F,
                          int32_t *agent_fill_counts, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): lob_exec_step with the same arguments, results
+ * and stream semantics, whose agent-order staging and step bookkeeping live in a
+ * static array of the library (2.25 MiB per GPU, held until the process ends)
+ * instead of the context's buffers.  It calls no allocating routine.  At most
+ * LOB_NOALLOC_MAX_BOOKS books per call (LOB_ECAP beyond).  Every call on one GPU
+ * uses that GPU's one array: calls that overlap on the device (other streams,
+ * other contexts, other host threads) race and must be serialised by the caller. */
+#define LOB_NOALLOC_MAX_BOOKS 16384
+lob_status lob_exec_step_noalloc(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window,
+                                 int32_t W, const int32_t *action_qty, const lob_exec_params *params,
+                                 lob_exec_state *state, int32_t *obs, double *reward, int32_t *agent_fills,
+                                 int32_t F, int32_t *agent_fill_counts, void *stream);
+
 /* ---------------------------------------------------------------- replay windows */
 
 /* Windowed replay data (Section 5.1.1, data loading).  Host memory only, no GPU

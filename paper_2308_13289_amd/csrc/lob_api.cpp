@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,41 @@
 namespace {
 
 thread_local std::string g_create_error;
+
+// Scratch of lob_exec_step_noalloc: agent-order staging [LOB_NOALLOC_MAX_BOOKS][4][8]
+// int32, then step bookkeeping [LOB_NOALLOC_MAX_BOOKS][2] int64 -- 2.25 MiB in the
+// library's device image, one copy per GPU, held until the process ends.  Host code
+// uses it only through the address hipGetSymbolAddress gives for each device.
+constexpr size_t kScratchActsBytes = sizeof(int32_t) * 4 * lob::kMsgFields * LOB_NOALLOC_MAX_BOOKS;
+constexpr size_t kScratchBytes = kScratchActsBytes + sizeof(int64_t) * 2 * LOB_NOALLOC_MAX_BOOKS;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The device address of `scratch` on the current device (once per device), or
+// nullptr with the error in *err.
+void *scratch_on_current_device(std::string *err) {
+  static std::mutex mu;
+  static std::vector<void *> addr;
+  static std::vector<int> state;  // 0 not looked up, 1 found, -1 failed
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+    *err = "no current device";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if ((size_t)dev >= addr.size()) {
+    addr.resize(dev + 1, nullptr);
+    state.resize(dev + 1, 0);
+  }
+  if (state[dev] == 0) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    state[dev] = (e == hipSuccess && p) ? 1 : -1;
+    addr[dev] = state[dev] == 1 ? p : nullptr;
+    if (state[dev] < 0) (void)hipGetLastError();
+  }
+  if (state[dev] < 0) *err = "the address of the static scratch array could not be found on this device";
+  return addr[dev];
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -159,6 +195,49 @@ lob_status run_process(lob_ctx *c, const lob::ProcArgs &a, hipStream_t s) {
 }
 
 
+// One execution step (lob_exec_step) with its agent-order staging acts [n][4][8] and
+// step bookkeeping aux [n][2] at the given device addresses.
+lob_status exec_step_with(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window, int32_t W,
+                          const int32_t *action_qty, const lob_exec_params *params, lob_exec_state *state,
+                          int32_t *obs, double *reward, int32_t *agent_fills, int32_t F, int32_t *agent_fill_counts,
+                          int32_t *acts, int64_t *aux, void *stream) {
+  if (W < 1 || W > 256) return fail(ctx, LOB_EINVAL, "W out of 1..256");
+  if (F < 1) return fail(ctx, LOB_EINVAL, "F < 1");
+  if (!params) return fail(ctx, LOB_EINVAL, "params is NULL");
+  if (n_books == 0) return LOB_OK;
+  if (!window || !aligned16(window)) return fail(ctx, LOB_EINVAL, "window NULL or not 16-byte aligned");
+  if (!action_qty || !state || !obs || !reward || !agent_fills || !agent_fill_counts)
+    return fail(ctx, LOB_EINVAL, "a buffer is NULL");
+  if ((reinterpret_cast<uintptr_t>(obs) & 3) || (reinterpret_cast<uintptr_t>(reward) & 7) ||
+      (reinterpret_cast<uintptr_t>(state) & 7))
+    return fail(ctx, LOB_EINVAL, "obs / reward / state misaligned");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = lob::launch_exec_prepare(ctx->d_hdr, ctx->d_books, book_ids, n_books, ctx->n_books, window, W,
+                                          action_qty, *params, state, acts, aux, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "exec prepare");
+  // the matcher: data then agent orders; level-1 row of every data message into the
+  // first 4W ints of the book's observation row; trades logged for the reward
+  lob::ProcArgs a = lob::base_args(ctx, book_ids, n_books);
+  a.msgs = window;
+  a.w1 = W;
+  a.msgs2 = acts;
+  a.w2 = 4;
+  a.l2_mode = LOB_L2_PER_MESSAGE;
+  a.levels = 1;
+  a.l2_out = obs;
+  a.l2_stride = 6 * (int64_t)W + 8;
+  a.fills = agent_fills;
+  a.fill_cap = F;
+  a.fill_counts = agent_fill_counts;
+  a.agent_tid = params->agent_tid;
+  lob_status st = run_process(ctx, a, s);
+  if (st != LOB_OK) return st;
+  e = lob::launch_exec_finish(ctx->d_hdr, book_ids, n_books, ctx->n_books, ctx->d_log, window, W, *params, state, obs,
+                              reward, agent_fills, F, agent_fill_counts, aux, s);
+  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "exec finish");
+}
+
 }  // namespace
 
 namespace lob {
@@ -261,6 +340,7 @@ lob_status lob_create(const lob_config *cfg, lob_ctx **out) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_ragged_done, hipEventDisableTiming);
+  if (e == hipSuccess) c->scratch = scratch_on_current_device(&c->scratch_err);
   if (e == hipSuccess) {  // advisory on this platform
     (void)lob::set_process_lds_limit(c->max_lds);
     (void)lob::set_process_unsorted_lds_limit(c->max_lds);
@@ -605,41 +685,23 @@ lob_status lob_exec_step(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books,
                          int32_t *agent_fill_counts, void *stream) {
   lob_status st = check_list(ctx, n_books);
   if (st != LOB_OK) return st;
-  if (W < 1 || W > 256) return fail(ctx, LOB_EINVAL, "W out of 1..256");
-  if (F < 1) return fail(ctx, LOB_EINVAL, "F < 1");
-  if (!params) return fail(ctx, LOB_EINVAL, "params is NULL");
-  if (n_books == 0) return LOB_OK;
-  if (!window || !aligned16(window)) return fail(ctx, LOB_EINVAL, "window NULL or not 16-byte aligned");
-  if (!action_qty || !state || !obs || !reward || !agent_fills || !agent_fill_counts)
-    return fail(ctx, LOB_EINVAL, "a buffer is NULL");
-  if ((reinterpret_cast<uintptr_t>(obs) & 3) || (reinterpret_cast<uintptr_t>(reward) & 7) ||
-      (reinterpret_cast<uintptr_t>(state) & 7))
-    return fail(ctx, LOB_EINVAL, "obs / reward / state misaligned");
-  DeviceGuard g(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = lob::launch_exec_prepare(ctx->d_hdr, ctx->d_books, book_ids, n_books, ctx->n_books, window, W,
-                                          action_qty, *params, state, ctx->d_exec_acts, ctx->d_exec_aux, s);
-  if (e != hipSuccess) return hip_fail(ctx, e, "exec prepare");
-  // the matcher: data then agent orders; level-1 row of every data message into the
-  // first 4W ints of the book's observation row; trades logged for the reward
-  lob::ProcArgs a = lob::base_args(ctx, book_ids, n_books);
-  a.msgs = window;
-  a.w1 = W;
-  a.msgs2 = ctx->d_exec_acts;
-  a.w2 = 4;
-  a.l2_mode = LOB_L2_PER_MESSAGE;
-  a.levels = 1;
-  a.l2_out = obs;
-  a.l2_stride = 6 * (int64_t)W + 8;
-  a.fills = agent_fills;
-  a.fill_cap = F;
-  a.fill_counts = agent_fill_counts;
-  a.agent_tid = params->agent_tid;
-  st = run_process(ctx, a, s);
+  return exec_step_with(ctx, book_ids, n_books, window, W, action_qty, params, state, obs, reward, agent_fills, F,
+                        agent_fill_counts, ctx->d_exec_acts, ctx->d_exec_aux, stream);
+}
+
+lob_status lob_exec_step_noalloc(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, const int32_t *window,
+                                 int32_t W, const int32_t *action_qty, const lob_exec_params *params,
+                                 lob_exec_state *state, int32_t *obs, double *reward, int32_t *agent_fills, int32_t F,
+                                 int32_t *agent_fill_counts, void *stream) {
+  lob_status st = check_list(ctx, n_books);
   if (st != LOB_OK) return st;
-  e = lob::launch_exec_finish(ctx->d_hdr, book_ids, n_books, ctx->n_books, ctx->d_log, window, W, *params, state, obs,
-                              reward, agent_fills, F, agent_fill_counts, ctx->d_exec_aux, s);
-  return e == hipSuccess ? LOB_OK : hip_fail(ctx, e, "exec finish");
+  if (n_books > LOB_NOALLOC_MAX_BOOKS)
+    return fail(ctx, LOB_ECAP, "lob_exec_step_noalloc: more than LOB_NOALLOC_MAX_BOOKS (16384) books in one call");
+  if (!ctx->scratch) return fail(ctx, LOB_EDEVICE, "lob_exec_step_noalloc: " + ctx->scratch_err);
+  int32_t *acts = reinterpret_cast<int32_t *>(ctx->scratch);
+  int64_t *aux = reinterpret_cast<int64_t *>(static_cast<unsigned char *>(ctx->scratch) + kScratchActsBytes);
+  return exec_step_with(ctx, book_ids, n_books, window, W, action_qty, params, state, obs, reward, agent_fills, F,
+                        agent_fill_counts, acts, aux, stream);
 }
 
 lob_status lob_read_l2(lob_ctx *ctx, const int32_t *book_ids, int32_t n_books, int32_t *l2_out, void *stream) {

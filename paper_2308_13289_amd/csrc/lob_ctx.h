@@ -71,6 +71,10 @@ struct lob_ctx {
   // its trades of the step start in its log, with its trade count [n_books][2]
   int32_t *d_exec_acts = nullptr;
   int64_t *d_exec_aux = nullptr;
+  // device address of the library's static scratch on this context's device
+  // (lob_exec_step_noalloc), or nullptr with the reason
+  void *scratch = nullptr;
+  std::string scratch_err;
 };
 
 

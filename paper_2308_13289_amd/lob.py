@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblob.so")
 OK, EINVAL, ENOMEM, EDEVICE, ECAP = 0, -1, -2, -3, -6
 L2_NONE, L2_PER_MESSAGE, L2_FINAL = 0, 1, 2
 MAX_CAPACITY, MAX_LEVELS = 4096, 64  # orders per side per book, L2 depth
+NOALLOC_MAX_BOOKS = 16384  # books per lob_exec_step_noalloc call
 BOOK_SIDE_FULL, BOOK_TIME_ORDER, BOOK_TRADE_FULL, BOOK_FILLS_FULL, BOOK_BAD_LOAD = 1, 2, 4, 8, 16
 
 STATUS_DTYPE = np.dtype([(n, np.int64) for n in (
@@ -68,7 +69,7 @@ _lib = None
 EXPORTS = ["lob_create", "lob_destroy", "lob_last_error", "lob_info", "lob_set_plan", "lob_get_plan",
            "lob_process_messages", "lob_process_ragged", "lob_autotune_ragged", "lob_step", "lob_read_l2", "lob_read_trades", "lob_read_status",
            "lob_read_book", "lob_write_book", "lob_reset", "lob_seed_l2", "lob_selftest", "lob_windows",
-           "lob_exec_step"]
+           "lob_exec_step", "lob_exec_step_noalloc"]
 
 
 def load(path=None):
@@ -116,6 +117,8 @@ def load(path=None):
     L.lob_reset.argtypes = [vp, vp, i32, vp]
     L.lob_exec_step.restype = i32
     L.lob_exec_step.argtypes = [vp, vp, i32, vp, i32, vp, ctypes.POINTER(ExecParams), vp, vp, vp, vp, i32, vp, vp]
+    L.lob_exec_step_noalloc.restype = i32
+    L.lob_exec_step_noalloc.argtypes = L.lob_exec_step.argtypes
     L.lob_windows.restype = i32
     L.lob_windows.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, vp]
     L.lob_seed_l2.restype = i32
@@ -332,13 +335,15 @@ class Context:
         self._check(self._lib.lob_reset(self._h, ids, n, _stream(stream, self.device)))
 
     def exec_step(self, window, action_qty, state, obs, reward, fills, fill_counts, tick=100, passive_ticks=1,
-                  agent_tid=-1, keep_trades=False, lam=0.0, book_ids=None, stream=None):
-        """Execution-environment step (lob_exec_step): window[n][W][8], action_qty[n][4]
-        int32, state = uint8 device tensor of n * 48 bytes (EXEC_STATE_DTYPE), obs
-        [n][6W+8] int32, reward [n] float64, fills [n][F][6], fill_counts [n]."""
+                  agent_tid=-1, keep_trades=False, lam=0.0, book_ids=None, stream=None, noalloc=False):
+        """Execution-environment step (lob_exec_step, or lob_exec_step_noalloc with
+        noalloc=True): window[n][W][8], action_qty[n][4] int32, state = uint8 device
+        tensor of n * 48 bytes (EXEC_STATE_DTYPE), obs [n][6W+8] int32, reward [n]
+        float64, fills [n][F][6], fill_counts [n]."""
         ids, n = self._ids(book_ids, window.shape[0])
         p = ExecParams(int(tick), int(passive_ticks), int(agent_tid), int(bool(keep_trades)), float(lam))
-        self._check(self._lib.lob_exec_step(
+        fn = self._lib.lob_exec_step_noalloc if noalloc else self._lib.lob_exec_step
+        self._check(fn(
             self._h, ids, n, _ptr(window, torch.int32, "window"), int(window.shape[1]),
             _ptr(action_qty, torch.int32, "action_qty"), ctypes.byref(p), _ptr(state, torch.uint8, "state"),
             _ptr(obs, torch.int32, "obs"), _ptr(reward, torch.float64, "reward"), _ptr(fills, torch.int32, "fills"),

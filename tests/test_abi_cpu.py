@@ -71,5 +71,5 @@ def test_binding_constants_match_the_header():
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(LOB_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text)}
     for name in ("OK", "EINVAL", "ENOMEM", "EDEVICE", "ECAP", "L2_NONE", "L2_PER_MESSAGE", "L2_FINAL",
                  "MAX_CAPACITY", "MAX_LEVELS", "BOOK_SIDE_FULL", "BOOK_TIME_ORDER", "BOOK_TRADE_FULL",
-                 "BOOK_FILLS_FULL", "BOOK_BAD_LOAD"):
+                 "BOOK_FILLS_FULL", "BOOK_BAD_LOAD", "NOALLOC_MAX_BOOKS"):
         assert getattr(lob, name) == defs["LOB_" + name], name
