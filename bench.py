@@ -223,8 +223,8 @@ def verify_books(ctx, w, l2, ids):
 def bench_ragged(args, n_books=10_000, reps=3):
     """Ragged batch: 10,000 books, capacity in {50,100,500,1000}, flow length
     log-uniform in [1e2, 1e5]; one autotuned lob_process_ragged call against the
-    plain kernel run once per capacity bucket (lob_process_messages, whole books in
-    LDS, one launch after the other)."""
+    plain kernel run once per capacity bucket (lob_process_messages, each launch
+    sized for its bucket's capacity, one launch after the other)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     t0 = time.perf_counter()
@@ -258,11 +258,14 @@ def bench_ragged(args, n_books=10_000, reps=3):
                         torch.zeros((len(ids), 2, LEVELS, 2), dtype=torch.int32, device=dev)))
 
     def plain():
+        # each bucket's launch is sized for its own capacity (plan max_capacity): cap
+        # 50 and 100 run the register kernel without a tail, cap 500 and 1000 with one
         for c, d_ids, d_bm, d_bo, bl2 in buckets:
-            ctx.set_plan(lds_slots=c, books_per_block=4)
+            ctx.set_plan(lds_slots=c, books_per_block=4, max_capacity=c)
             ctx.process(d_bm, d_bo, book_ids=d_ids, l2_mode=lob.L2_FINAL, l2_out=bl2, stream=stream)
 
     plain_ms, plain_all = timed(plain)
+    ctx.set_plan(max_capacity=0)
     t1 = time.perf_counter()
     plan, tuned_ms = ctx.autotune_ragged(d_msgs, w.offs, max_trials=args.tune_trials, stream=stream)
     tune_s = time.perf_counter() - t1

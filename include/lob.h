@@ -153,6 +153,14 @@ typedef struct {
                               a search of the whole side per trade and per cancel
                               -- with the whole book in LDS (for comparison; same
                               results; capacity limited by LDS)                 */
+  int32_t max_capacity;    /* lob_process_messages, lob_step and lob_exec_step: 0 =
+                              size each launch for the context's largest capacity;
+                              > 0 = the listed books' capacities are at most this,
+                              and each launch takes the kernel form, window and
+                              occupancy of that capacity (a listed book above it
+                              is left untouched and flagged LOB_BOOK_BAD_LOAD).
+                              lob_process_ragged and the server size each launch
+                              from the capacities of the books it holds.        */
 } lob_plan;
 
 typedef struct lob_ctx lob_ctx;

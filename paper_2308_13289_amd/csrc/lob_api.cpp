@@ -190,8 +190,14 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
   return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
 }
 
+// The capacity bound of a lob_process_messages / lob_step / lob_exec_step launch:
+// the plan's, else the context's largest.
+int plan_cap_limit(const lob_ctx *c) {
+  return c->plan.max_capacity > 0 ? std::min(c->plan.max_capacity, c->max_cap) : c->max_cap;
+}
+
 lob_status run_process(lob_ctx *c, const lob::ProcArgs &a, hipStream_t s) {
-  return launch(c, a, c->plan.lds_slots, c->max_cap, c->plan.books_per_block, s);
+  return launch(c, a, c->plan.lds_slots, plan_cap_limit(c), c->plan.books_per_block, s);
 }
 
 
@@ -255,6 +261,9 @@ ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n) {
   return a;
 }
 lob_status launch_with_plan(lob_ctx *c, const ProcArgs &a, hipStream_t s) { return run_process(c, a, s); }
+lob_status launch_with_cap(lob_ctx *c, const ProcArgs &a, int cap_limit, hipStream_t s) {
+  return launch(c, a, c->plan.lds_slots, std::max(1, std::min(cap_limit, c->max_cap)), c->plan.books_per_block, s);
+}
 lob_status set_error(lob_ctx *c, lob_status st, const std::string &msg) { return fail(c, st, msg); }
 }  // namespace lob
 
@@ -392,6 +401,7 @@ lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan) {
     return fail(ctx, LOB_EINVAL, "books_per_block_big");
   if (plan->registers != 0 && plan->registers != 1) return fail(ctx, LOB_EINVAL, "registers");
   if (plan->layout != 0 && plan->layout != 1) return fail(ctx, LOB_EINVAL, "layout");
+  if (plan->max_capacity < 0 || plan->max_capacity > LOB_MAX_CAPACITY) return fail(ctx, LOB_EINVAL, "max_capacity");
   if (plan->layout == 1 && (size_t)lob::unsorted_lds_ints(ctx->max_cap) * sizeof(int32_t) > ctx->max_lds)
     return fail(ctx, LOB_ECAP, "layout 1: the largest book does not fit in LDS");
   for (int w : {plan->lds_slots, plan->lds_slots_big, plan->ragged_split > 0 ? plan->ragged_split : 1})
@@ -508,10 +518,15 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
     ctx->ragged_pending = true;
     return LOB_OK;
   };
+  // each launch is sized for the largest capacity among the books it holds
+  auto max_cap_of = [&](const std::vector<int32_t> &v) {
+    int m = 1;
+    for (int32_t i : v) m = std::max(m, (int)ctx->caps[book_ids_host ? book_ids_host[i] : i]);
+    return m;
+  };
+  const int cap_small = max_cap_of(small);
   if (big.empty())
-    return done(launch(ctx, a, p.ragged_split > 0 ? p.ragged_split : p.lds_slots,
-                       p.ragged_split > 0 ? std::min(p.ragged_split, ctx->max_cap) : ctx->max_cap,
-                       p.books_per_block, s));
+    return done(launch(ctx, a, p.ragged_split > 0 ? p.ragged_split : p.lds_slots, cap_small, p.books_per_block, s));
   // two buckets: the large-capacity launch on the side stream, forked from and
   // joined back into the caller's stream
   lob::ProcArgs b = a;
@@ -521,10 +536,9 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
   b.n = (int32_t)big.size();
   if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return hip_fail(ctx, e, "fork");
   if ((e = hipStreamWaitEvent(ctx->side_stream, ctx->ev_fork, 0)) != hipSuccess) return hip_fail(ctx, e, "fork");
-  if ((st = launch(ctx, b, p.lds_slots_big, ctx->max_cap, p.books_per_block_big, ctx->side_stream)) != LOB_OK)
+  if ((st = launch(ctx, b, p.lds_slots_big, max_cap_of(big), p.books_per_block_big, ctx->side_stream)) != LOB_OK)
     return st;
-  if ((st = launch(ctx, a, p.ragged_split, std::min(p.ragged_split, ctx->max_cap), p.books_per_block, s)) != LOB_OK)
-    return st;
+  if ((st = launch(ctx, a, p.ragged_split, cap_small, p.books_per_block, s)) != LOB_OK) return st;
   if ((e = hipEventRecord(ctx->ev_join, ctx->side_stream)) != hipSuccess) return hip_fail(ctx, e, "join");
   if ((e = hipStreamWaitEvent(s, ctx->ev_join, 0)) != hipSuccess) return hip_fail(ctx, e, "join");
   return done(LOB_OK);

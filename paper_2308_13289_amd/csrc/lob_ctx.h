@@ -82,6 +82,8 @@ namespace lob {
 // Launch the matching kernel over a.n listed books with the context's plan (or the
 // given window / books per workgroup); defined in lob_api.cpp.
 lob_status launch_with_plan(lob_ctx *c, const ProcArgs &a, hipStream_t s);
+// The same over books whose capacities are at most cap_limit (known on the host).
+lob_status launch_with_cap(lob_ctx *c, const ProcArgs &a, int cap_limit, hipStream_t s);
 lob_status set_error(lob_ctx *c, lob_status st, const std::string &msg);
 ProcArgs base_args(lob_ctx *c, const int32_t *ids, int32_t n);
 }  // namespace lob

@@ -419,6 +419,10 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds, int W) {
   st.n[0] = uni(h->n[0]);
   st.n[1] = uni(h->n[1]);
   st.cap = uni(h->cap);
+  if (!SPILL && st.cap > W) {  // a book above the launch's capacity bound: left untouched
+    if (l == 0) h->flags |= kFlagBadLoad;
+    return;
+  }
   st.flags = uni(h->flags);
   st.n_msgs = uni64(h->n_msgs);
   st.n_trades = uni64(h->n_trades);

@@ -8,8 +8,10 @@
 //              the slot's share of the HBM staging budget
 //   slots      n_slots batches in flight, each on its own stream with its own
 //              pinned + device staging; a batch = one matching launch (one wave
-//              per book: its messages, then its agent orders), one trade-log
-//              drain for its books, one copy of the outputs back to pinned memory
+//              per book: its messages, then its agent orders) over books of one
+//              capacity class (<= 128 or larger, so that the launch is sized for
+//              its own books), one trade-log drain for its books, one copy of the
+//              outputs back to pinned memory
 //   retire     when a slot's event has completed, results are copied into the
 //              requests' host buffers and their books are free again
 #include <hip/hip_runtime.h>
@@ -163,11 +165,19 @@ lob_status launch_batch(lob_server *s, Slot &sl) {
   const size_t limit = std::min(s->queue.size(), (size_t)8 * s->cfg.max_batch + 4096);
   std::vector<int64_t> take, keep;
   int64_t msgs = 0, room = 0;
+  // one batch holds books of one class -- sides that fit in registers (capacity
+  // <= 128) or larger -- so that its single launch takes the form and occupancy of
+  // its own books; the class is the first eligible request's
+  constexpr int kRegCap = 128;
+  int batch_class = -1;
+  int cap_bound = 1;
   for (size_t k = 0; k < limit; ++k) {
     const int64_t qi = s->queue.front();
     s->queue.pop_front();
     const lob_request &r = s->table[qi].r;
-    bool ok = (int32_t)take.size() < s->cfg.max_batch && !s->on_device[r.book] && s->seen[r.book] != scan;
+    const int cls = c->caps[r.book] <= kRegCap ? 0 : 1;
+    bool ok = (int32_t)take.size() < s->cfg.max_batch && !s->on_device[r.book] && s->seen[r.book] != scan &&
+              (batch_class < 0 || cls == batch_class);
     const int64_t tb = trade_bound(c, r);
     if (ok && (msgs + r.n_msgs > s->max_msgs || room + tb > s->max_trade_room)) ok = false;
     s->seen[r.book] = scan;  // later requests of this book wait for a later batch
@@ -175,6 +185,8 @@ lob_status launch_batch(lob_server *s, Slot &sl) {
       take.push_back(qi);
       msgs += r.n_msgs;
       room += tb;
+      batch_class = cls;
+      cap_bound = std::max(cap_bound, (int)c->caps[r.book]);
     } else {
       keep.push_back(qi);
     }
@@ -221,7 +233,7 @@ lob_status launch_batch(lob_server *s, Slot &sl) {
   a.fill_cap = s->cfg.fill_cap;
   a.fill_counts = reinterpret_cast<int32_t *>(sl.d + y.fcounts);
   a.agent_tid = s->cfg.agent_tid;
-  lob_status st = lob::launch_with_plan(c, a, sl.stream);
+  lob_status st = lob::launch_with_cap(c, a, cap_bound, sl.stream);
   if (st != LOB_OK) return st;
   e = lob::launch_read_trades(c->d_hdr, c->d_log, a.book_ids, n, c->n_books,
                               reinterpret_cast<int32_t *>(sl.d + y.trades), room,

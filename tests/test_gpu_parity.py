@@ -478,3 +478,35 @@ def test_autotune_ragged_keeps_results_exact():
     g = run_gpu(w.caps, w.msgs, w.offs, l2_mode=lob.L2_FINAL, ctx=ctx, ragged=True)
     o = run_oracle(w.caps, w.msgs, w.offs, l2_mode=O.L2_FINAL)
     assert_same(g, o, f"after autotune {plan}")
+
+
+@pytest.mark.parametrize("res", ["regs", "lds", "unsorted"])
+def test_plan_max_capacity_bounds_the_launch(res):
+    """Plan max_capacity sizes lob_process_messages launches for the listed books:
+    books within the bound give the oracle's results; a listed book above it is
+    left untouched and flagged LOB_BOOK_BAD_LOAD."""
+    w = W.ragged(n_books=24, max_flow=1500)
+    caps = w.caps.copy()
+    lens = np.diff(w.offs)
+    bound = 100
+    small = np.nonzero(caps <= bound)[0].astype(np.int32)
+    big = np.nonzero(caps > bound)[0].astype(np.int32)
+    assert len(small) and len(big)
+    ctx = new_context(caps, 10, lens, plan=dict(RESIDENCY[res], max_capacity=bound))
+    listed = np.concatenate([small, big[:1]]).astype(np.int32)
+    sel = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in listed])
+    offs = np.concatenate([[0], np.cumsum(lens[listed])]).astype(np.int64)
+    l2 = torch.zeros((len(listed), 2, 10, 2), dtype=torch.int32, device="cuda:0")
+    ctx.process(to_dev(w.msgs[sel]), to_dev(offs), book_ids=to_dev(listed), l2_mode=lob.L2_FINAL, l2_out=l2)
+    st = ctx.read_status()
+    assert st["flags"][big[0]] & lob.BOOK_BAD_LOAD
+    assert st["n_msgs"][big[0]] == 0 and st["n_ask"][big[0]] == 0 and st["n_bid"][big[0]] == 0
+    o = run_oracle(caps[small], w.msgs[np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in small])],
+                   np.concatenate([[0], np.cumsum(lens[small])]).astype(np.int64), l2_mode=O.L2_FINAL)
+    np.testing.assert_array_equal(l2.cpu().numpy()[:len(small)], o["l2"])
+    book = ctx.read_book(int(caps.max()), book_ids=to_dev(small)).cpu().numpy()
+    np.testing.assert_array_equal(book[:, :, :o["dumps"].shape[2]], o["dumps"])
+    assert (book[:, :, o["dumps"].shape[2]:] == -1).all()
+    for k in COUNTERS:
+        np.testing.assert_array_equal(st[k][small], o["stats"][k], err_msg=k)
+    ctx.close()
