@@ -37,12 +37,12 @@ assert STATS_DTYPE.itemsize == ctypes.sizeof(Stats)
 
 
 def build(force=False):
-    """Compile liboracle.so with gcc (plain C11, -O2)."""
+    """Compile liboracle.so with gcc (plain C11, -O3)."""
     if not force and os.path.exists(BUILT) and os.path.getmtime(BUILT) >= max(
             os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "lob_oracle.h"))):
         return BUILT
     tmp = BUILT + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+    subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
                            "-pthread", SRC, "-o", tmp])
     os.replace(tmp, BUILT)
     return BUILT
@@ -133,6 +133,16 @@ def trade_bound(n_msgs):
     return 2 * np.asarray(n_msgs, dtype=np.int64)
 
 
+def default_threads():
+    """Worker threads when the caller names none: the cores this process may use,
+    at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def run(caps, msgs, offs, l2_mode=L2_NONE, levels=10, trade_room=None, dumps=False,
         dump_cap=None, threads=None):
     """Run every book's stream through the oracle.
@@ -163,7 +173,7 @@ def run(caps, msgs, offs, l2_mode=L2_NONE, levels=10, trade_room=None, dumps=Fal
         l2 = None
     dcap = int(dump_cap or (caps.max() if n else 1))
     dump_arr = np.zeros((n, 2, dcap, 6), np.int32) if dumps else None
-    nt = threads or os.cpu_count() or 1
+    nt = threads or default_threads()
     rc = lib().orc_run(n, _p32(caps), _p32(msgs), _p64(offs), l2_mode, levels, _p32(l2),
                        _p32(trades), _p64(toffs), _p64(tmsg), _p64(counts), stats.ctypes.data,
                        _p32(dump_arr), dcap, nt)

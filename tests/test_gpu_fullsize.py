@@ -1,7 +1,9 @@
 """Parity at the full sizes the benchmark runs, in the launch configuration it times
 (default plan; the ragged path autotuned; the step form as one captured graph;
-the serving loop at full book count), on sampled books the oracle replays one by
-one (tolerance 0: everything is integer)."""
+the serving loop at full book count), against the oracle's replay of the same
+streams (tolerance 0: everything is integer): every book of the uniform batch, every
+book of capacity <= 100 and 200 larger ones of the ragged batch, 64 books over all
+1000 steps of the step form, 256 books of the serving run."""
 import numpy as np
 import pytest
 import torch
@@ -24,9 +26,12 @@ LEVELS = 10
 
 def check_books(ctx, w, l2, ids):
     ids = np.asarray(ids, np.int32)
-    sel = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in ids])
-    soffs = np.concatenate([[0], np.cumsum(np.diff(w.offs)[ids])]).astype(np.int64)
-    o = O.run(w.caps[ids], w.msgs[sel], soffs, l2_mode=O.L2_FINAL, levels=LEVELS, dumps=True,
+    if len(ids) == w.n_books and (ids == np.arange(w.n_books)).all():
+        msgs, soffs = w.msgs, w.offs
+    else:
+        msgs = w.msgs[np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in ids])]
+        soffs = np.concatenate([[0], np.cumsum(np.diff(w.offs)[ids])]).astype(np.int64)
+    o = O.run(w.caps[ids], msgs, soffs, l2_mode=O.L2_FINAL, levels=LEVELS, dumps=True,
               dump_cap=int(w.caps.max()))
     d_ids = to_dev(ids)
     total = int(ctx.read_status(d_ids)["log_records"].sum())
@@ -38,14 +43,14 @@ def check_books(ctx, w, l2, ids):
     np.testing.assert_array_equal(book.cpu().numpy(), o["dumps"])
 
 
-def test_c1_full_size_sampled():
-    """4096 books x (100 + 10,000) messages, capacity 100, one launch."""
+def test_c1_full_size_every_book():
+    """4096 books x (100 + 10,000) messages, capacity 100, one launch; every book's
+    trades, final L2, final book and counters."""
     w = W.c1()
     ctx = lob.Context(w.caps, l2_levels=LEVELS, trade_log_records=w.caps.astype(np.int64) + 2 * np.diff(w.offs))
     l2 = torch.zeros((w.n_books, 2, LEVELS, 2), dtype=torch.int32, device="cuda:0")
     ctx.process(to_dev(w.msgs), to_dev(w.offs), l2_mode=lob.L2_FINAL, l2_out=l2)
-    ids = np.sort(np.random.default_rng(11).choice(w.n_books, 12, replace=False))
-    check_books(ctx, w, l2, np.concatenate([[0, w.n_books - 1], ids]))
+    check_books(ctx, w, l2, np.arange(w.n_books))
     st = ctx.read_status()
     # a side may fill up (a flagged, counted rejection the oracle reproduces); nothing else
     assert (st["flags"] & ~lob.BOOK_SIDE_FULL == 0).all(), np.unique(st["flags"])
@@ -53,9 +58,9 @@ def test_c1_full_size_sampled():
     assert ((st["flags"] & lob.BOOK_SIDE_FULL) != 0).sum() == (st["rejected_qty"] > 0).sum()
 
 
-def test_c2_full_size_ragged_autotuned_sampled():
-    """10,000 ragged books (148M messages) through the autotuned ragged path; the
-    longest book, the largest capacity and random books checked."""
+def test_c2_full_size_ragged_autotuned():
+    """10,000 ragged books (148M messages) through the autotuned ragged path; every
+    book of capacity <= 100, the longest book and 200 random larger books checked."""
     w = W.ragged(10_000)
     lens = np.diff(w.offs)
     ctx = lob.Context(w.caps, l2_levels=LEVELS, trade_log_records=w.caps.astype(np.int64) + 2 * lens)
@@ -65,16 +70,16 @@ def test_c2_full_size_ragged_autotuned_sampled():
     l2 = torch.zeros((w.n_books, 2, LEVELS, 2), dtype=torch.int32, device="cuda:0")
     ctx.process_ragged(d_msgs, w.offs, l2_mode=lob.L2_FINAL, l2_out=l2)
     rng = np.random.default_rng(12)
-    big = np.nonzero(w.caps == w.caps.max())[0]
-    ids = np.unique(np.concatenate([[int(np.argmax(lens))], rng.choice(big, 3, replace=False),
-                                    rng.choice(w.n_books, 8, replace=False)]))
+    small = np.nonzero(w.caps <= 100)[0]
+    big = np.nonzero(w.caps > 100)[0]
+    ids = np.unique(np.concatenate([small, [int(np.argmax(lens))], rng.choice(big, 200, replace=False)]))
     check_books(ctx, w, l2, ids)
 
 
-def test_c3_full_size_graph_sampled():
+def test_c3_full_size_graph():
     """8192 books x 1000 steps of (100 data messages + up to 4 agent orders), all
-    steps captured as one graph; sampled books' L2 and agent fills after every step
-    equal the oracle's replay of the same stream."""
+    steps captured as one graph; 64 books' L2 and agent fills after every one of the
+    1000 steps equal the oracle's replay of the same streams."""
     n_books, n_steps, window, F = 8192, 1000, 100, 32
     w = W.step_workload(n_books=n_books, n_steps=n_steps, window=window)
     seeds = w.extra["seed_msgs"]
@@ -100,26 +105,38 @@ def test_c3_full_size_graph_sampled():
     g.replay()
     torch.cuda.synchronize()
     g_l2, g_f, g_c = l2.cpu().numpy(), fills.cpu().numpy(), counts.cpu().numpy()
-    for b in np.random.default_rng(13).choice(n_books, 6, replace=False):
+    books = np.sort(np.random.default_rng(13).choice(n_books, 64, replace=False))
+    per_book = seeds + n_steps * (window + 4)
+    streams = []
+    for b in books:
         stream = [host[b, :seeds]]
         for s in range(n_steps):
             stream += [host[b, seeds + s * window:seeds + (s + 1) * window], acts[b, s]]
-        msgs = np.concatenate(stream)
-        o = O.run(w.caps[b:b + 1], msgs, np.array([0, len(msgs)], np.int64), l2_mode=O.L2_PER_MESSAGE,
-                  levels=LEVELS)
-        tm, tr = o["trade_msg"], o["trades"]
-        for s in range(n_steps):
-            last = seeds + (s + 1) * (window + 4) - 1
-            np.testing.assert_array_equal(g_l2[s, b], o["l2"][last], err_msg=f"book {b} step {s}")
-            sel = (tm > last - (window + 4)) & (tm <= last) & ((tr[:, 6] == -1) | (tr[:, 7] == -1))
-            want = tr[sel, :6]
-            assert g_c[s, b] == len(want), (b, s)
-            np.testing.assert_array_equal(g_f[s, b, :min(len(want), F)], want[:F])
+        streams.append(np.concatenate(stream))
+    msgs = np.concatenate(streams)
+    offs = np.arange(len(books) + 1, dtype=np.int64) * per_book
+    o = O.run(w.caps[books], msgs, offs, l2_mode=O.L2_PER_MESSAGE, levels=LEVELS)
+    ends = seeds + (np.arange(n_steps) + 1) * (window + 4) - 1  # last message of each step
+    for k, b in enumerate(books):
+        np.testing.assert_array_equal(g_l2[:, b], o["l2"][k * per_book + ends], err_msg=f"book {b}")
+        tr = o["trades"][o["trade_offs"][k]:o["trade_offs"][k + 1]]
+        tm = o["trade_msg"][o["trade_offs"][k]:o["trade_offs"][k + 1]] - k * per_book
+        ag = ((tr[:, 6] == -1) | (tr[:, 7] == -1)) & (tm >= seeds)
+        step = np.searchsorted(ends, tm[ag])  # the step of each agent fill's message (in order)
+        cnt = np.bincount(step, minlength=n_steps)
+        np.testing.assert_array_equal(g_c[:, b], cnt, err_msg=f"book {b}: fills per step")
+        # the first min(count, F) fills of every step, gathered in one go
+        kept = np.minimum(cnt, F)
+        first = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        j = np.arange(kept.sum()) - np.repeat(np.cumsum(kept) - kept, kept)
+        want = tr[ag][np.repeat(first, kept) + j, :6]
+        np.testing.assert_array_equal(g_f[np.repeat(np.arange(n_steps), kept), b, j], want, err_msg=f"book {b}")
 
 
-def test_c4_full_book_count_serving_sampled():
+def test_c4_full_book_count_serving():
     """The serving loop over 20,000 resident books of mixed capacity at 200k
-    requests/s; sampled books equal the oracle replaying them in arrival order."""
+    requests/s; 256 books' requests equal the oracle replaying them in arrival
+    order."""
     sw = S.ServingWorkload(n_books=20_000, lam=200_000, duration_s=0.1)
     room = 2 * sw.caps.astype(np.int64) + 2 * (1000 + 4)
     ctx = lob.Context(sw.caps, l2_levels=LEVELS, trade_log_records=room)
@@ -131,7 +148,7 @@ def test_c4_full_book_count_serving_sampled():
     comp = S.Server(ctx, n_slots=4, hbm_budget=1 << 30, max_batch=4096).run(sw.requests(), sw.arrival)
     assert len(comp) == sw.n and (comp["status"] == lob.OK).all()
     n_out = dict(zip(comp["tag"], comp["n_out"]))
-    books = [int(b) for b in np.random.default_rng(14).choice(np.unique(sw.book), 24, replace=False)]
+    books = [int(b) for b in np.random.default_rng(14).choice(np.unique(sw.book), 256, replace=False)]
     msgs, offs, spans = sw.oracle_streams(books)
     r = O.run(sw.caps[np.asarray(books)], msgs, offs, l2_mode=O.L2_PER_MESSAGE, levels=LEVELS)
     tm, tr = r["trade_msg"], r["trades"]
