@@ -89,19 +89,33 @@ def load_traffic(name, khash):
     return load_profile(name, khash).get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, n_sample_books):
-    """The oracle (plain sequential C engine), as it stands, on a bounded sample of
-    the same workload, books spread over the host cores."""
+def cpu_baseline(w, n_sample_books, n_single_books=512):
+    """The oracle (plain sequential C engine, gcc -O3), as it stands, on a bounded
+    sample of the same workload: the books spread over this process's host cores (at
+    most 16, the CPU share of one GPU), and a smaller sample on one thread."""
     from oracle import oracle as O
-    n = min(n_sample_books, w.n_books)
-    offs = w.offs[:n + 1]
+
+    def timed(n, threads):
+        n = min(n, w.n_books)
+        offs = w.offs[:n + 1]
+        t0 = time.perf_counter()
+        O.run(w.caps[:n], w.msgs[:offs[-1]], offs, l2_mode=O.L2_FINAL, levels=LEVELS, threads=threads)
+        return n, int(offs[-1]), time.perf_counter() - t0
+
     cores = host_cores()
-    t0 = time.perf_counter()
-    O.run(w.caps[:n], w.msgs[:offs[-1]], offs, l2_mode=O.L2_FINAL, levels=LEVELS, threads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": float(offs[-1] / dt), "unit": "msgs/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} of {w.n_books} books ({int(offs[-1])} messages), final L2, "
-                      f"{dt:.2f} s wall on {cores} threads"}
+    n, m, dt = timed(n_sample_books, cores)
+    n1, m1, dt1 = timed(n_single_books, 1)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"value": float(m / dt), "unit": "msgs/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} of {w.n_books} books ({m} messages), final L2, {dt:.2f} s wall on {cores} "
+                      f"threads",
+            "single_thread": {"value": float(m1 / dt1), "unit": "msgs/s", "cores": 1,
+                              "sample": f"first {n1} books ({m1} messages), {dt1:.2f} s wall on 1 thread"},
+            "host": {"os_cpu_count": os.cpu_count(), "affinity_cpus": affinity,
+                     "threads_used": cores, "note": "threads capped at 16, the CPU share of one GPU"}}
 
 
 def verify_sample(ctx, w, l2, n_check=16, seed=1):
