@@ -436,6 +436,30 @@ lob_status lob_process_messages(lob_ctx *ctx, const int32_t *book_ids, int32_t n
   return run_process(ctx, a, (hipStream_t)stream);
 }
 
+// The pinned staging buffer is rewritten only after the copy of the previous
+// schedule out of it has completed.
+static lob_status stage_wait(lob_ctx *ctx) {
+  if (!ctx->staged_pending) return LOB_OK;
+  hipError_t e = hipEventSynchronize(ctx->ev_staged);
+  if (e != hipSuccess) return hip_fail(ctx, e, "staging wait");
+  ctx->staged_pending = false;
+  return LOB_OK;
+}
+
+// Copy the first `bytes` of the staging buffer to the device schedule.  The device
+// copy is reused: the copy waits for the kernels of the previous ragged call,
+// whichever stream it was issued on.
+static lob_status stage_copy(lob_ctx *ctx, size_t bytes, hipStream_t s) {
+  hipError_t e;
+  if (ctx->ragged_pending && (e = hipStreamWaitEvent(s, ctx->ev_ragged_done, 0)) != hipSuccess)
+    return hip_fail(ctx, e, "ragged order");
+  if ((e = hipMemcpyAsync(ctx->d_stage, ctx->h_stage, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(ctx, e, "staging copy");
+  if ((e = hipEventRecord(ctx->ev_staged, s)) != hipSuccess) return hip_fail(ctx, e, "staging event");
+  ctx->staged_pending = true;
+  return LOB_OK;
+}
+
 lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books, const int32_t *msgs,
                               const int64_t *msg_offsets_host, int32_t l2_mode, int32_t *l2_out, void *stream) {
   lob_status st = check_list(ctx, n_books);
@@ -470,10 +494,7 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
   // stage [ids | rows | ranges] in pinned memory, one copy to the device
   DeviceGuard g(ctx->device);
   hipError_t e;
-  if (ctx->staged_pending) {
-    if ((e = hipEventSynchronize(ctx->ev_staged)) != hipSuccess) return hip_fail(ctx, e, "staging wait");
-    ctx->staged_pending = false;
-  }
+  if ((st = stage_wait(ctx)) != LOB_OK) return st;
   int32_t *h_ids = ctx->h_stage;
   int32_t *h_rows = h_ids + n_books;
   int64_t *h_ranges = reinterpret_cast<int64_t *>(ctx->h_stage + 2 * (size_t)n_books);  // 8n bytes: aligned
@@ -488,14 +509,7 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
     }
   const size_t bytes = reinterpret_cast<char *>(h_ranges + 2 * (size_t)n_books) - reinterpret_cast<char *>(h_ids);
   hipStream_t s = (hipStream_t)stream;
-  // the device copy of the schedule is reused: wait for the kernels of the previous
-  // ragged call, whichever stream it was issued on
-  if (ctx->ragged_pending && (e = hipStreamWaitEvent(s, ctx->ev_ragged_done, 0)) != hipSuccess)
-    return hip_fail(ctx, e, "ragged order");
-  if ((e = hipMemcpyAsync(ctx->d_stage, ctx->h_stage, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
-    return hip_fail(ctx, e, "staging copy");
-  if ((e = hipEventRecord(ctx->ev_staged, s)) != hipSuccess) return hip_fail(ctx, e, "staging event");
-  ctx->staged_pending = true;
+  if ((st = stage_copy(ctx, bytes, s)) != LOB_OK) return st;
   const int32_t *d_ids = ctx->d_stage;
   const int32_t *d_rows = d_ids + n_books;
   const int64_t *d_ranges =
@@ -599,12 +613,25 @@ lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32
   std::vector<int32_t> caps;
   for (int32_t i = 0; i < n_books; ++i) {
     const int32_t b = book_ids_host ? book_ids_host[i] : i;
-    if (b >= 0 && b < ctx->n_books) caps.push_back(ctx->caps[b]);
+    if (b < 0 || b >= ctx->n_books) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(ctx, LOB_EINVAL, "book id out of range");
+    }
+    caps.push_back(ctx->caps[b]);
   }
   std::sort(caps.begin(), caps.end());
   caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
-  const int maxc = caps.empty() ? ctx->max_cap : caps.back();
-  lob_status r = LOB_OK;
+  const int maxc = caps.back();
+  // the untimed first run of the first candidate starts from empty books too: stage
+  // the listed ids where reset_listed reads them and reset the books
+  lob_status r = stage_wait(ctx);
+  if (r == LOB_OK) {
+    for (int32_t i = 0; i < n_books; ++i) ctx->h_stage[i] = book_ids_host ? book_ids_host[i] : i;
+    r = stage_copy(ctx, sizeof(int32_t) * (size_t)n_books, s);
+  }
+  if (r == LOB_OK) r = reset_listed();
+  if (r != LOB_OK) goto out;
   // stage 1: structure -- one launch with whole books in LDS or a small window,
   // or two buckets split at each listed capacity below the largest
   {
