@@ -134,6 +134,16 @@ __device__ __forceinline__ void tail_move(const Tail &t, int lo, int hi, int d) 
   }
 }
 
+// Lanes l >= k (0 <= k < 64).  TAIL form: taken straight from a scalar mask (one
+// scalar shift instead of a vector compare), which measured faster there.
+template <bool TAIL>
+__device__ __forceinline__ bool from_k(int k) {
+  if constexpr (TAIL)
+    return __builtin_amdgcn_inverse_ballot_w64(~0ull << k);
+  else
+    return lane_id() >= k;
+}
+
 __device__ __forceinline__ void pick(Chunk &x, bool c, const Chunk &v) {
   x.p = c ? v.p : x.p;
   x.q = c ? v.q : x.q;
@@ -149,7 +159,9 @@ struct RState {
   int cap, flags;
   int small_lim;  // min(capacity, 64): below it an insert without a tail needs no other test
   int trades, misses;
-  long long cancelled_qty, market_discarded, rejected_qty;
+  // cancel_short: of the cancelled quantities requested, the part no order gave up
+  // (the request beyond the order's quantity, or all of it when no order has the id)
+  long long cancel_short, market_discarded, rejected_qty;
   int last_ts, last_tns, seen;
   int32_t *log;  // the book's next free log record, or nullptr
   int log_room;  // records that still fit in the log
@@ -190,9 +202,10 @@ __device__ __forceinline__ bool agent_msg(const RState &st, const int4 &v, int j
 struct Stage {
   int p, q, po, j;
   int k;
-  // per-lane running sums of submitted limit and market quantities and of traded
-  // quantities, reduced over the wave once at the end of the call
-  unsigned long long limit_qty, market_qty, traded_qty;
+  // per-lane running sums of submitted limit and market quantities, of the
+  // quantities cancel messages ask to remove and of traded quantities, reduced over
+  // the wave once at the end of the call
+  unsigned long long limit_qty, market_qty, traded_qty, cancel_qty;
 };
 
 // Sum over the wave of a non-negative int32 per lane, as 64-bit.
@@ -389,7 +402,7 @@ __device__ __forceinline__ void remove_at(Side &S, const Tail &tl, int k, int n)
     } else {
       shift_dn<!TAIL>(S.c1, l + kWave >= k);
       if (k < kWave) {
-        shift_dn<!TAIL>(S.c0, l >= k);
+        shift_dn<!TAIL>(S.c0, from_k<TAIL>(k));
         put(S.c0, in, 63);
       }
     }
@@ -399,7 +412,7 @@ __device__ __forceinline__ void remove_at(Side &S, const Tail &tl, int k, int n)
   } else if (front) {
     shift_dn_all(S.c0);
   } else {
-    shift_dn<!TAIL>(S.c0, l >= k);
+    shift_dn<!TAIL>(S.c0, from_k<TAIL>(k));
   }
 }
 
@@ -467,7 +480,7 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 // X: what the launch collects besides trades and final L2 -- bit 0 agent fills,
 // bit 1 per-message L2 (the checks for what it does not collect are compiled out);
 // bit 2 selects the rotating-priority variant.
-// LIMIT: a limit order, which more often than not rests untouched (a layout hint).
+// LIMIT: a limit order that crosses (the caller has tested rests_apart).
 // The aggressor is message j of the chunk v = (OID, TID, Ts, Tns) across the lanes.
 template <int OPP, bool TAIL, int X, bool LIMIT>
 __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, int q, const int4 &v, int j) {
@@ -475,10 +488,13 @@ __device__ __forceinline__ int match(Book &bk, RState &st, Stage &sg, int lim, i
   const Tail &tl = bk.tl[OPP];
   int n = st.n[OPP];
   constexpr bool buyer = (OPP == 0);
-  if (LOB_UNLIKELY(n == 0)) return q;  // q > 0: the decode turns messages with Q <= 0 into no-ops
+  // a limit order gets here only when it crosses (rests_apart is false)
+  if constexpr (!LIMIT) {
+    if (LOB_UNLIKELY(n == 0)) return q;  // q > 0: the decode turns messages with Q <= 0 into no-ops
+    const int bp0 = rdlane(S.c0.p, 0);
+    if (LOB_UNLIKELY(buyer ? bp0 > lim : bp0 < lim)) return q;
+  }
   const int bp = rdlane(S.c0.p, 0);
-  const bool apart = buyer ? bp > lim : bp < lim;  // the best standing price does not overlap
-  if (LIMIT ? LOB_LIKELY(apart) : LOB_UNLIKELY(apart)) return q;
   const int bq = rdlane(S.c0.q, 0);
   if (LOB_LIKELY(q <= bq)) {
     // Q_s' = Q_s - Q_a >= 0: one trade with the best order fills the aggressor
@@ -606,6 +622,18 @@ __device__ __forceinline__ bool ahead_timed(bool held, int p, int h, int P, int 
   return ahead;
 }
 
+// Whether a limit order at price lim meets no standing order of side OPP: the side
+// is empty or its best price does not overlap lim.  Lane 0 is read before the count
+// is tested (it holds some value either way), so that the common outcome, a best
+// price apart from lim, takes one test.
+template <int OPP>
+__device__ __forceinline__ bool rests_apart(const Book &bk, const RState &st, int lim) {
+  const Side &S = OPP == 0 ? bk.ask : bk.bid;
+  const int bp = rdlane(S.c0.p, 0);
+  if (LOB_LIKELY(OPP == 0 ? bp > lim : bp < lim)) return true;
+  return st.n[OPP] == 0;
+}
+
 // Add (Section 4.1, item 1) on side SD: the new order goes to its price-time
 // position.  While a book's times have never gone backwards every standing order is
 // at most as old as the new one, so that position is behind every order with an
@@ -624,7 +652,8 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
     // without a tail a side rarely holds 64 orders: then only chunk 0 takes part,
     // and one test covers the capacity too
     if (LOB_LIKELY(n < st.small_lim)) {
-      const int at = popc(lt_mask(l, n) & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
+      const uint64_t live = (1ull << n) - 1;  // n < 64 here
+      const int at = popc(live & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
       Chunk v;
       v.p = P;
       v.q = Q;
@@ -702,7 +731,7 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
     if (pos < kWave) put(S.c1, in, 0);
   }
   if (LOB_LIKELY(pos < kWave)) {
-    shift_up<!TAIL>(S.c0, l >= pos);
+    shift_up<!TAIL>(S.c0, from_k<TAIL>(pos));
     put(S.c0, v, pos);
   } else {
     put(S.c1, v, pos - kWave);
@@ -733,15 +762,15 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
   const int n = st.n[SD];
   const int nr = n < kSlots ? n : kSlots;
   int k = -1;
-  uint64_t m = lt_mask(l, nr) & eq_mask(S.c0.o, oid);
+  uint64_t m = lt_mask(l, n) & eq_mask(S.c0.o, oid);  // (l < 64: the same as l < nr)
   if (LOB_LIKELY(m != 0)) {
     // the common case, an order in chunk 0 found by its id
     const int k0 = first_set(m);
     const int Q = rdlane(S.c0.q, k0);
-    st.cancelled_qty += (unsigned)min(qty, Q);
     if (LOB_LIKELY(Q > qty)) {
       S.c0.q = wl(S.c0.q, Q - qty, k0);
     } else {
+      st.cancel_short += (unsigned)(qty - Q);
       remove_at<TAIL>(S, tl, k0, n);
       st.n[SD] = n - 1;
     }
@@ -772,6 +801,7 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
   }
   if (k < 0 && t < 0) {
     st.misses++;
+    st.cancel_short += (unsigned)qty;
     return;
   }
   if constexpr (TAIL) {
@@ -779,11 +809,11 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
       const int T = n - kSlots;
       const int4 e = tl.a[t];
       const int P = uni(e.x), Q = uni(e.y);
-      st.cancelled_qty += min(qty, Q);
       const int left = Q - qty;
       if (left > 0) {
         if (l == 0) tl.a[t] = make_int4(P, left, uni(e.z), uni(e.w));
       } else {
+        st.cancel_short += (unsigned)(qty - Q);
         tail_move(tl, t + 1, T, -1);  // the entries above it (better priority) move down by one
         st.n[SD] = n - 1;
       }
@@ -793,7 +823,6 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
   const bool lo = k < kWave;
   const int kl = k & 63;
   const int Q = lo ? rdlane(S.c0.q, kl) : rdlane(S.c1.q, kl);
-  st.cancelled_qty += (unsigned)min(qty, Q);
   const int left = Q - qty;
   if (left > 0) {
     if (lo)
@@ -801,6 +830,7 @@ __device__ __forceinline__ void cancel(Book &bk, RState &st, int oid, int qty, i
     else
       S.c1.q = wl(S.c1.q, left, kl);
   } else {
+    st.cancel_short += (unsigned)(qty - Q);
     remove_at<TAIL>(S, tl, k, n);
     st.n[SD] = n - 1;
   }
@@ -882,11 +912,12 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
   if (LOB_LIKELY(code < 2)) {
     const int P = rdlane(u.z, j), Q = rdlane(u.w, j);
     __builtin_assume(Q > 0);  // the decode gives messages with Q <= 0 code 7
+    // most limit orders meet no standing order and rest whole
     if (code == 0) {
-      const int rem = match<1, TAIL, X, true>(bk, st, sg, P, Q, v, j);
+      const int rem = rests_apart<1>(bk, st, P) ? Q : match<1, TAIL, X, true>(bk, st, sg, P, Q, v, j);
       if (rem > 0) insert<0, TAIL, TIMED>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j), v, j, pk);
     } else {
-      const int rem = match<0, TAIL, X, true>(bk, st, sg, P, Q, v, j);
+      const int rem = rests_apart<0>(bk, st, P) ? Q : match<0, TAIL, X, true>(bk, st, sg, P, Q, v, j);
       if (rem > 0) insert<1, TAIL, TIMED>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j), v, j, pk);
     }
   } else if (code < 4) {
@@ -975,18 +1006,28 @@ __device__ __forceinline__ bool process_all(Book &bk, RState &st, Stage &sg, con
       const int qpos = u.w > 0 ? u.w : 0;
       sg.limit_qty += (unsigned)(code < 2 ? qpos : 0);
       sg.market_qty += (unsigned)((code >> 1) == 2 ? qpos : 0);
+      sg.cancel_qty += (unsigned)((code >> 1) == 1 ? qpos : 0);
     }
     if constexpr ((X & 1) != 0 && kAgentMask<TAIL, X>) st.agm = ballot(v.y == st.agent_tid);
     // messages of this chunk that come from source 1 (they get per-message L2 rows)
     const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
     if (LOB_LIKELY(!(st.flags & kFlagTimeOrder))) {
+      // Without agent fills the next message's case is read one message ahead, so
+      // that the lane read is off the dispatch's dependency chain (measured faster
+      // there; with agent fills, slower).
+      int c = rdlane(code, 0);
 #pragma nounroll
       for (int j = 0; j < cnt; ++j) {
-        const int c = rdlane(code, j);
+        int cn = 0;
+        if constexpr ((X & 1) == 0)
+          cn = rdlane(code, (j + 1) & (kWave - 1));
+        else
+          c = rdlane(code, j);
         process_msg<TAIL, X, false>(bk, st, sg, c, u, v, j, (int)k0 + j, pk);
         if constexpr ((X & 2) != 0) {
           if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
         }
+        if constexpr ((X & 1) == 0) c = cn;
       }
     } else if constexpr (kTimedInline<TAIL, X>) {
       // a book whose times went backwards: the same loop with the timed insert
@@ -1150,7 +1191,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   }
   st.small_lim = st.cap < kWave ? st.cap : kWave;
   st.trades = st.misses = 0;
-  st.cancelled_qty = st.market_discarded = st.rejected_qty = 0;
+  st.cancel_short = st.market_discarded = st.rejected_qty = 0;
   st.last_ts = uni(h->last_ts);
   st.last_tns = uni(h->last_tns);
   st.seen = uni(h->seen_time);
@@ -1198,7 +1239,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   Stage sg;
   sg.p = sg.q = sg.po = sg.j = 0;
   sg.k = 0;
-  sg.limit_qty = sg.market_qty = sg.traded_qty = 0;
+  sg.limit_qty = sg.market_qty = sg.traded_qty = sg.cancel_qty = 0;
 
   // ragged launches raise the longest streams' waves for good; launches whose waves
   // share SIMDs (X bit 2) rotate priorities (rank: the wave's slot on its SIMD, bits
@@ -1271,6 +1312,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
   }
   const long long limit_qty = wave_sum64(sg.limit_qty), market_qty = wave_sum64(sg.market_qty),
                   traded_qty = wave_sum64(sg.traded_qty);
+  const long long cancelled_qty = wave_sum64(sg.cancel_qty) - st.cancel_short;
   if (l == 0) {
     h->book_off = off_out;
     h->n[0] = st.n[0];
@@ -1281,7 +1323,7 @@ __device__ void run_book(const ProcArgs &a, int i, int2 *lds) {
     h->limit_qty += limit_qty;
     h->market_qty += market_qty;
     h->traded_qty += traded_qty;
-    h->cancelled_qty += st.cancelled_qty;
+    h->cancelled_qty += cancelled_qty;
     h->market_discarded += st.market_discarded;
     h->rejected_qty += st.rejected_qty;
     h->cancel_miss += st.misses;
