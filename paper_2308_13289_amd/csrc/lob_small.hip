@@ -186,6 +186,14 @@ constexpr bool kAgentMask = !TAIL && (X & 2) == 0;
 template <bool TAIL, int X>
 constexpr bool kTimedInline = !TAIL && (X & 2) == 0;
 
+// The next message's case read one message ahead, off the dispatch's dependency
+// chain, for two more scalar moves per message: faster where few waves share a SIMD
+// (the TAIL form's large books, the rotating variant's 2 to 4 waves per SIMD) and
+// latency bounds a book; slower with agent fills, and with 8 or more waves per SIMD
+// (the variant without rotation), where issue does.
+template <bool TAIL, int X>
+constexpr bool kReadAhead = (X & 1) == 0 && (TAIL || (X & 4) != 0);
+
 template <bool TAIL, int X>
 __device__ __forceinline__ bool agent_msg(const RState &st, const int4 &v, int j) {
   if constexpr (kAgentMask<TAIL, X>)
@@ -1012,14 +1020,11 @@ __device__ __forceinline__ bool process_all(Book &bk, RState &st, Stage &sg, con
     // messages of this chunk that come from source 1 (they get per-message L2 rows)
     const int c1 = (int)(n1 - k0 < 0 ? 0 : (n1 - k0 < cnt ? n1 - k0 : cnt));
     if (LOB_LIKELY(!(st.flags & kFlagTimeOrder))) {
-      // Without agent fills the next message's case is read one message ahead, so
-      // that the lane read is off the dispatch's dependency chain (measured faster
-      // there; with agent fills, slower).
       int c = rdlane(code, 0);
 #pragma nounroll
       for (int j = 0; j < cnt; ++j) {
         int cn = 0;
-        if constexpr ((X & 1) == 0)
+        if constexpr (kReadAhead<TAIL, X>)
           cn = rdlane(code, (j + 1) & (kWave - 1));
         else
           c = rdlane(code, j);
@@ -1027,7 +1032,7 @@ __device__ __forceinline__ bool process_all(Book &bk, RState &st, Stage &sg, con
         if constexpr ((X & 2) != 0) {
           if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
         }
-        if constexpr ((X & 1) == 0) c = cn;
+        if constexpr (kReadAhead<TAIL, X>) c = cn;
       }
     } else if constexpr (kTimedInline<TAIL, X>) {
       // a book whose times went backwards: the same loop with the timed insert
