@@ -664,7 +664,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
                     choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout", "occupancy"])
-    ap.add_argument("--tune-trials", type=int, default=16)
+    ap.add_argument("--tune-trials", type=int, default=18)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")

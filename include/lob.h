@@ -221,13 +221,16 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
                               int32_t l2_mode, int32_t *l2_out, void *stream);
 
 /* Autotuner for lob_process_ragged: runs the batch under candidate plans -- one
- * launch or two capacity buckets, LDS window sizes (books larger than the window
- * keep their tail in HBM), books per workgroup -- times each candidate with HIP
- * events on `stream` as the slowest of three runs after one untimed run, installs
- * the fastest plan in the context and returns it with that time.  Every run
- * starts from empty books: the listed books are reset before each run and left
- * reset at the end (their previous state is lost).  At most max_trials candidates
- * (>= 1), four runs each.  Waits for the device (not graph-capturable). */
+ * launch or two capacity buckets, the LDS engine or the paper's unsorted layout
+ * (Section 4) in one launch, LDS window sizes (books larger than the window keep
+ * their tail in HBM), books per workgroup -- times each candidate with HIP events
+ * on `stream` as the slowest of three runs after one untimed run, installs the
+ * fastest plan in the context and returns it with that time.  Every run starts
+ * from empty books: the listed ids are checked (LOB_EINVAL if one is out of range,
+ * before anything runs) and the listed books reset before each run and left reset
+ * at the end (their previous state is lost).  At most max_trials candidates (>= 1),
+ * four runs each; a candidate that does not fit (LDS) is skipped and not counted.
+ * Waits for the device (not graph-capturable). */
 lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books,
                                const int32_t *msgs, const int64_t *msg_offsets_host,
                                int32_t max_trials, lob_plan *best, float *best_ms, void *stream);

@@ -652,6 +652,18 @@ lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32
         if ((r = trial(p)) != LOB_OK) goto out;
       }
     }
+    // the other residencies in one launch: the LDS engine alone, and the paper's
+    // unsorted arrays (skipped when the largest book does not fit in LDS)
+    lob_plan q = base;
+    q.ragged_order = 1;
+    q.ragged_split = 0;
+    q.books_per_block = 4;
+    q.lds_slots = std::min(128, maxc);
+    q.registers = 0;
+    if ((r = trial(q)) != LOB_OK) goto out;
+    q.registers = base.registers;
+    q.layout = 1;
+    if ((r = trial(q)) != LOB_OK) goto out;
   }
   // stage 2: books per workgroup of each launch
   {
