@@ -476,26 +476,66 @@ def bench_step(args, n_books=8192, n_steps=1000, window=100, fills_cap=32):
     torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     eager_out = (l2[-1].clone(), counts.sum().item())
-    # graph: all steps captured once, replayed
+    # graph: all steps captured once, replayed.  With chains > 1 the books are split
+    # into that many groups, each stepping through its own chain of launches on its
+    # own stream inside the graph (the groups are independent, as the books are): a
+    # group's next step starts while the other groups' last waves of this step run.
     seed()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
+    chains = max(1, args.step_chains)
+    bounds = np.linspace(0, n_books, chains + 1).astype(int)
+    ids = [torch.arange(bounds[c], bounds[c + 1], dtype=torch.int32, device=dev) for c in range(chains)]
+    side = [torch.cuda.Stream(dev) for _ in range(chains - 1)]
     with torch.cuda.graph(g):
+        cap = torch.cuda.current_stream(dev)
+        fork = torch.cuda.Event()
+        fork.record(cap)
+        for st in side:
+            st.wait_event(fork)
         for s in range(n_steps):
-            one(s, None)
-    reps = []
-    for _ in range(max(1, args.graph_reps)):
+            if chains == 1:
+                one(s, None)
+                continue
+            for c in range(chains):
+                lo, hi = int(bounds[c]), int(bounds[c + 1])
+                st = cap if c == 0 else side[c - 1]
+                ctx.step(d_win[s, lo:hi], l2[s, lo:hi], actions=d_act[s, lo:hi], book_ids=ids[c], agent_tid=-1,
+                         fills=fills[s, lo:hi], fill_counts=counts[s, lo:hi], stream=st)
+        for st in side:
+            join = torch.cuda.Event()
+            join.record(st)
+            cap.wait_event(join)
+    def replays(graph):
+        out = []
+        for _ in range(max(1, args.graph_reps)):
+            seed()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            graph.replay()
+            torch.cuda.synchronize()
+            out.append(time.perf_counter() - t1)
+        return out
+
+    reps = replays(g)
+    same = bool(torch.equal(l2[-1], eager_out[0]) and counts.sum().item() == eager_out[1])
+    one_chain = None
+    if chains > 1:  # the same steps as one chain of launches over all books, for reference
+        del g
+        g1 = torch.cuda.CUDAGraph()
         seed()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        g.replay()
-        torch.cuda.synchronize()
-        reps.append(time.perf_counter() - t1)
-    same = bool(torch.equal(l2[-1], eager_out[0]) and counts.sum().item() == eager_out[1])
+        with torch.cuda.graph(g1):
+            for s in range(n_steps):
+                one(s, None)
+        one_chain = n_steps / min(replays(g1))
+        same = same and bool(torch.equal(l2[-1], eager_out[0]) and counts.sum().item() == eager_out[1])
+        del g1
     total_msgs = n_books * n_steps * window + n_act
     best = min(reps)
     res = {"workload": f"{n_books} books x {n_steps} steps x ({window} data msgs + 0-4 agent orders), "
                        f"capacity 100, L2 + agent fills per step, hipGraph of all steps",
+           "graph_chains": chains, "steps_per_s_one_chain": one_chain,
            "steps_per_s": n_steps / best, "msgs_per_s": total_msgs / best,
            "graph_s": best, "graph_replays_s": reps,
            "eager_step_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
@@ -666,6 +706,8 @@ def main():
                     choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout", "occupancy"])
     ap.add_argument("--tune-trials", type=int, default=18)
     ap.add_argument("--graph-reps", type=int, default=2)
+    ap.add_argument("--step-chains", type=int, default=2,
+                    help="step form: book groups stepping in independent chains inside the graph")
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

@@ -1,5 +1,6 @@
 """Parity at the full sizes the benchmark runs, in the launch configuration it times
-(default plan; the ragged path autotuned; the step form as one captured graph;
+(default plan; the ragged path autotuned; the step form as one captured graph of
+two chains;
 the serving loop at full book count), against the oracle's replay of the same
 streams (tolerance 0: everything is integer): every book of the uniform batch, every
 book of capacity <= 100 and 200 larger ones of the ragged batch, 64 books over all
@@ -78,8 +79,9 @@ def test_c2_full_size_ragged_autotuned():
 
 def test_c3_full_size_graph():
     """8192 books x 1000 steps of (100 data messages + up to 4 agent orders), all
-    steps captured as one graph; 64 books' L2 and agent fills after every one of the
-    1000 steps equal the oracle's replay of the same streams."""
+    steps captured as one graph (two chains of launches over the two halves of the
+    books); 64 books' L2 and agent fills after every one of the 1000 steps equal the
+    oracle's replay of the same streams."""
     n_books, n_steps, window, F = 8192, 1000, 100, 32
     w = W.step_workload(n_books=n_books, n_steps=n_steps, window=window)
     seeds = w.extra["seed_msgs"]
@@ -97,11 +99,25 @@ def test_c3_full_size_graph():
     counts = torch.zeros((n_steps, n_books), dtype=torch.int32, device="cuda:0")
     ctx.process(d_seed, to_dev(np.arange(n_books + 1, dtype=np.int64) * seeds))
     torch.cuda.synchronize()
+    # as the benchmark times it: two halves of the books, each a chain of step launches
+    # on its own stream inside the one graph
+    half = n_books // 2
+    ids = [torch.arange(0, half, dtype=torch.int32, device="cuda:0"),
+           torch.arange(half, n_books, dtype=torch.int32, device="cuda:0")]
+    side = torch.cuda.Stream()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
+        cap = torch.cuda.current_stream()
+        fork = torch.cuda.Event()
+        fork.record(cap)
+        side.wait_event(fork)
         for s in range(n_steps):
-            ctx.step(d_win[s], l2[s], actions=d_act[s], agent_tid=-1, fills=fills[s], fill_counts=counts[s],
-                     stream=None)
+            for c, (lo, hi, st) in enumerate(((0, half, cap), (half, n_books, side))):
+                ctx.step(d_win[s, lo:hi], l2[s, lo:hi], actions=d_act[s, lo:hi], book_ids=ids[c], agent_tid=-1,
+                         fills=fills[s, lo:hi], fill_counts=counts[s, lo:hi], stream=st)
+        join = torch.cuda.Event()
+        join.record(side)
+        cap.wait_event(join)
     g.replay()
     torch.cuda.synchronize()
     g_l2, g_f, g_c = l2.cpu().numpy(), fills.cpu().numpy(), counts.cpu().numpy()
