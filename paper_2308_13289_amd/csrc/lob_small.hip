@@ -18,8 +18,9 @@
 // once costs four lane-selects and no store.
 //
 // Per 64 messages the lanes decode the message cases, check that times do not
-// decrease and add the submitted limit / market quantity to per-lane sums; the
-// scalar path per message only dispatches on the case.
+// decrease and add the submitted limit / market quantities and the quantities
+// cancels ask to remove to per-lane sums; the scalar path per message only
+// dispatches on the case.
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <stdint.h>
