@@ -704,7 +704,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
                     choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout", "occupancy"])
-    ap.add_argument("--tune-trials", type=int, default=18)
+    ap.add_argument("--tune-trials", type=int, default=19)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--step-chains", type=int, default=2,
                     help="step form: book groups stepping in independent chains inside the graph")

@@ -161,6 +161,12 @@ typedef struct {
                               is left untouched and flagged LOB_BOOK_BAD_LOAD).
                               lob_process_ragged and the server size each launch
                               from the capacities of the books it holds.        */
+  int32_t tail_shallow;    /* 1: launches of books larger than 128 orders per side
+                              (no agent fills, no per-message L2) take the code
+                              laid out for sides the flow has drained below 64
+                              orders (faster there, slower for books that stay
+                              deep); 0 = laid out for deep books.  The ragged
+                              autotuner tries both.                              */
 } lob_plan;
 
 typedef struct lob_ctx lob_ctx;

@@ -142,6 +142,7 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
     const bool step = a.msgs && !a.offs && !a.ranges;  // fixed windows of w1 messages
     a.rotate = (a.prio_len == 0 && n > simds && (n <= 4 * simds || step)) ? 1 : 0;
   }
+  a.tail_shallow = c->plan.tail_shallow;
   if (c->plan.layout == 1) {  // the paper's unsorted arrays, whole book in LDS
     const int per_wave = (lob::unsorted_lds_ints(cap_limit) + 1) / 2;
     int b = std::max(1, std::min(16, bpb));
@@ -402,6 +403,7 @@ lob_status lob_set_plan(lob_ctx *ctx, const lob_plan *plan) {
   if (plan->registers != 0 && plan->registers != 1) return fail(ctx, LOB_EINVAL, "registers");
   if (plan->layout != 0 && plan->layout != 1) return fail(ctx, LOB_EINVAL, "layout");
   if (plan->max_capacity < 0 || plan->max_capacity > LOB_MAX_CAPACITY) return fail(ctx, LOB_EINVAL, "max_capacity");
+  if (plan->tail_shallow != 0 && plan->tail_shallow != 1) return fail(ctx, LOB_EINVAL, "tail_shallow");
   if (plan->layout == 1 && (size_t)lob::unsorted_lds_ints(ctx->max_cap) * sizeof(int32_t) > ctx->max_lds)
     return fail(ctx, LOB_ECAP, "layout 1: the largest book does not fit in LDS");
   for (int w : {plan->lds_slots, plan->lds_slots_big, plan->ragged_split > 0 ? plan->ragged_split : 1})
@@ -665,6 +667,13 @@ lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32
     q.layout = 1;
     if ((r = trial(q)) != LOB_OK) goto out;
   }
+  // stage 1b: the TAIL form's code for drained books, when the batch has books above
+  // 128 orders per side
+  if (maxc > lob::small_book_slots()) {
+    lob_plan p = best_p;
+    p.tail_shallow = 1 - p.tail_shallow;
+    if ((r = trial(p)) != LOB_OK) goto out;
+  }
   // stage 2: books per workgroup of each launch
   {
     const lob_plan s1 = best_p;
@@ -692,6 +701,7 @@ lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32
       if ((r = trial(p)) != LOB_OK) goto out;
     }
   }
+
 out:
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

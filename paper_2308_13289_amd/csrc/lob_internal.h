@@ -87,6 +87,9 @@ struct ProcArgs {
   // (set by the host when a launch has more books than the GPU has SIMDs, so that
   // waves share SIMDs)
   int32_t rotate;
+  // 1: launches of the TAIL form without agent fills and per-message L2 take the
+  // instantiation laid out for sides of fewer than 64 orders (plan.tail_shallow)
+  int32_t tail_shallow;
 };
 
 }  // namespace lob

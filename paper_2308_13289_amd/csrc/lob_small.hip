@@ -195,6 +195,14 @@ constexpr bool kTimedInline = !TAIL && (X & 2) == 0;
 template <bool TAIL, int X>
 constexpr bool kReadAhead = (X & 1) == 0 && (TAIL || (X & 4) != 0);
 
+// The chunk-0 insert of a side of fewer than 64 orders as its own path: always
+// without a tail; with one only in the instantiation for books that the flow drains
+// (X bit 3): it saves the tail form's work on chunk 1 there, and costs books that
+// stay deep 6-9% (register copies where the paths merge), so the autotuner picks
+// the instantiation per batch.
+template <bool TAIL, int X>
+constexpr bool kChunk0Insert = !TAIL || (X & 8) != 0;
+
 template <bool TAIL, int X>
 __device__ __forceinline__ bool agent_msg(const RState &st, const int4 &v, int j) {
   if constexpr (kAgentMask<TAIL, X>)
@@ -488,7 +496,7 @@ __device__ __forceinline__ void shift_front(Side &S, int m, int n) {
 // with limit price lim and quantity q.  Returns the unfilled quantity.
 // X: what the launch collects besides trades and final L2 -- bit 0 agent fills,
 // bit 1 per-message L2 (the checks for what it does not collect are compiled out);
-// bit 2 selects the rotating-priority variant.
+// bit 2 selects the rotating-priority variant, bit 3 the TAIL form's chunk-0 insert.
 // LIMIT: a limit order that crosses (the caller has tested rests_apart).
 // The aggressor is message j of the chunk v = (OID, TID, Ts, Tns) across the lanes.
 template <int OPP, bool TAIL, int X, bool LIMIT>
@@ -649,7 +657,7 @@ __device__ __forceinline__ bool rests_apart(const Book &bk, const RState &st, in
 // equal or better price; in a book flagged for times going backwards (TIMED) the
 // times of the orders at the new order's price are compared too (ahead_timed).
 // hnd: the new order's handle; it is message j of the chunk v = (OID, TID, Ts, Tns).
-template <int SD, bool TAIL, bool TIMED>
+template <int SD, bool TAIL, bool TIMED, bool CHUNK0 = !TAIL>
 __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int oid, int hnd, const int4 &v_,
                                        int j, int pk) {
   static_assert(!(TAIL && TIMED), "the TAIL form leaves such books to the LDS engine");
@@ -657,9 +665,9 @@ __device__ __forceinline__ void insert(Book &bk, RState &st, int P, int Q, int o
   const Tail &tl = bk.tl[SD];
   const int l = lane_id();
   const int n = st.n[SD];
-  if constexpr (!TAIL && !TIMED) {
-    // without a tail a side rarely holds 64 orders: then only chunk 0 takes part,
-    // and one test covers the capacity too
+  if constexpr (CHUNK0 && !TIMED) {
+    // a side of fewer than 64 orders (without a tail the rule; with one, a book the
+    // flow has drained): only chunk 0 takes part, and one test covers the capacity
     if (LOB_LIKELY(n < st.small_lim)) {
       const uint64_t live = (1ull << n) - 1;  // n < 64 here
       const int at = popc(live & (SD == 1 ? ge_mask(S.c0.p, P) : le_mask(S.c0.p, P)));
@@ -924,10 +932,14 @@ __device__ __forceinline__ void process_msg(Book &bk, RState &st, Stage &sg, int
     // most limit orders meet no standing order and rest whole
     if (code == 0) {
       const int rem = rests_apart<1>(bk, st, P) ? Q : match<1, TAIL, X, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<0, TAIL, TIMED>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j), v, j, pk);
+      if (rem > 0)
+        insert<0, TAIL, TIMED, kChunk0Insert<TAIL, X>>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j),
+                                                       v, j, pk);
     } else {
       const int rem = rests_apart<0>(bk, st, P) ? Q : match<0, TAIL, X, true>(bk, st, sg, P, Q, v, j);
-      if (rem > 0) insert<1, TAIL, TIMED>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j), v, j, pk);
+      if (rem > 0)
+        insert<1, TAIL, TIMED, kChunk0Insert<TAIL, X>>(bk, st, P, rem, rdlane(v.x, j), handle<TAIL, X>(st, k, v, j),
+                                                       v, j, pk);
     }
   } else if (code < 4) {
     if (code == 2)
@@ -1371,11 +1383,12 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int grid = (a.n + a.bpb - 1) / a.bpb;
   const size_t lds = tail ? (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2) : 0;
   // X: bit 0 agent fills, bit 1 per-message L2, bit 2 rotating priorities (without a
-  // tail only)
-  const int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0) | (!tail && a.rotate ? 4 : 0);
-  switch ((tail ? 8 : 0) | x) {
+  // tail only), bit 3 the TAIL form's chunk-0 insert (kChunk0Insert; alone only)
+  int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0) | (!tail && a.rotate ? 4 : 0);
+  if (tail && x == 0 && a.tail_shallow) x = 8;
+  switch ((tail ? 16 : 0) | x) {
 #define LOB_SMALL_CASE(T, X)                                                                   \
-  case (T ? 8 : 0) | X:                                                                        \
+  case (T ? 16 : 0) | X:                                                                       \
     hipLaunchKernelGGL((k_process_small<T, X>), dim3(grid), dim3(threads), T ? lds : 0, s, a); \
     break;
     LOB_SMALL_CASE(false, 0)
@@ -1390,14 +1403,16 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
     LOB_SMALL_CASE(true, 1)
     LOB_SMALL_CASE(true, 2)
     LOB_SMALL_CASE(true, 3)
+    LOB_SMALL_CASE(true, 8)
 #undef LOB_SMALL_CASE
   }
   return hipGetLastError();
 }
 
 hipError_t set_process_small_lds_limit(size_t bytes) {
-  const void *k[4] = {(const void *)k_process_small<true, 0>, (const void *)k_process_small<true, 1>,
-                      (const void *)k_process_small<true, 2>, (const void *)k_process_small<true, 3>};
+  const void *k[5] = {(const void *)k_process_small<true, 0>, (const void *)k_process_small<true, 1>,
+                      (const void *)k_process_small<true, 2>, (const void *)k_process_small<true, 3>,
+                      (const void *)k_process_small<true, 8>};
   for (const void *f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;

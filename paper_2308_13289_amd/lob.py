@@ -59,7 +59,8 @@ class Plan(ctypes.Structure):
     _fields_ = [("lds_slots", ctypes.c_int32), ("books_per_block", ctypes.c_int32),
                 ("ragged_split", ctypes.c_int32), ("lds_slots_big", ctypes.c_int32),
                 ("ragged_order", ctypes.c_int32), ("books_per_block_big", ctypes.c_int32),
-                ("registers", ctypes.c_int32), ("layout", ctypes.c_int32), ("max_capacity", ctypes.c_int32)]
+                ("registers", ctypes.c_int32), ("layout", ctypes.c_int32), ("max_capacity", ctypes.c_int32),
+                ("tail_shallow", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

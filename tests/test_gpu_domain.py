@@ -29,7 +29,8 @@ from paper_2308_13289_amd import lob  # noqa: E402
 from test_oracle_bruteforce import PREFIX_BIG, alphabet, alphabet_big, to_msgs  # noqa: E402
 
 BIG = 2 ** 31 - 1
-PLANS = {"regs": {"registers": 1}, "tail": {"registers": 1}, "lds": {"registers": 0},
+PLANS = {"regs": {"registers": 1}, "tail": {"registers": 1}, "tail_shallow": {"registers": 1, "tail_shallow": 1},
+         "lds": {"registers": 0},
          "spill": {"registers": 0, "lds_slots": 64}, "unsorted": {"layout": 1}}
 # one more book of this capacity in the same call puts the register kernel in its
 # TAIL form (and gives the LDS kernels a window past 128)
@@ -45,7 +46,7 @@ def with_tail_book(caps, msgs, offs):
 def compare(caps, msgs, offs, res, levels, l2_mode=lob.L2_PER_MESSAGE, calls=1):
     caps = np.asarray(caps, np.int32)
     offs = np.asarray(offs, np.int64)
-    if res == "tail":
+    if res.startswith("tail"):
         caps, msgs, offs = with_tail_book(caps, msgs, offs)
     g = run_gpu(caps, msgs, offs, levels=levels, l2_mode=l2_mode, plan=PLANS[res], calls=calls)
     o = run_oracle(caps, msgs, offs, levels=levels, l2_mode=l2_mode)
@@ -108,7 +109,7 @@ def flow(rng, n_books, n_msgs, cap, big, shuffled_times, mid=10_000_000, tick=10
     return np.full(n_books, cap, np.int32), np.concatenate(books), offs
 
 
-@pytest.mark.parametrize("res", ["regs", "tail", "lds", "unsorted"])
+@pytest.mark.parametrize("res", ["regs", "tail", "tail_shallow", "lds", "unsorted"])
 @pytest.mark.parametrize("cap", [2, 3])
 def test_bruteforce_large_quantities(cap, res):
     """Every length-3 sequence of the large-quantity alphabet after two initial
@@ -119,7 +120,7 @@ def test_bruteforce_large_quantities(cap, res):
     compare(np.full(len(streams), cap, np.int32), msgs, offs, res, levels=2)
 
 
-@pytest.mark.parametrize("res", ["regs", "tail", "lds", "unsorted"])
+@pytest.mark.parametrize("res", ["regs", "tail", "tail_shallow", "lds", "unsorted"])
 @pytest.mark.parametrize("cap", [2, 3])
 def test_bruteforce_times_out_of_order(cap, res):
     """Random sequences of the small alphabet with times from a few values."""
@@ -134,7 +135,7 @@ def test_bruteforce_times_out_of_order(cap, res):
     assert (o["stats"]["flags"] & lob.BOOK_TIME_ORDER).any()
 
 
-@pytest.mark.parametrize("res", ["regs", "tail", "lds", "spill", "unsorted"])
+@pytest.mark.parametrize("res", ["regs", "tail", "tail_shallow", "lds", "spill", "unsorted"])
 @pytest.mark.parametrize("cap", [100, 300])
 def test_flow_large_quantities(cap, res):
     if res == "tail" and cap > 128:
@@ -147,7 +148,7 @@ def test_flow_large_quantities(cap, res):
     assert (o["l2"][..., 1] == BIG).any()
 
 
-@pytest.mark.parametrize("res", ["regs", "tail", "lds", "spill", "unsorted"])
+@pytest.mark.parametrize("res", ["regs", "tail", "tail_shallow", "lds", "spill", "unsorted"])
 @pytest.mark.parametrize("cap", [100, 300])
 @pytest.mark.parametrize("l2", ["per_message", "final"])
 @pytest.mark.parametrize("calls", [1, 3])

@@ -48,18 +48,20 @@ def test_selftest_primitives():
 
 
 RESIDENCY = {"regs": {"registers": 1}, "lds": {"registers": 0}, "unsorted": {"layout": 1},
-             "tail": {"registers": 1}}
+             "tail": {"registers": 1}, "tail_shallow": {"registers": 1, "tail_shallow": 1}}
 
 
-@pytest.mark.parametrize("res", ["regs", "lds", "unsorted", "tail"])
+@pytest.mark.parametrize("res", ["regs", "lds", "unsorted", "tail", "tail_shallow"])
 def test_golden_cases_on_gpu(res):
     """The hand-worked cases; "tail" adds a book of capacity 300 to the call, which
-    puts the register kernel in its TAIL form for every book."""
+    puts the register kernel in its TAIL form for every book ("tail_shallow": the
+    TAIL form's code for drained books)."""
     cases = all_cases()
-    caps = np.array([c.cap for c in cases] + ([300] if res == "tail" else []), np.int32)
+    tail = res.startswith("tail")
+    caps = np.array([c.cap for c in cases] + ([300] if tail else []), np.int32)
     msgs = np.concatenate([c.msgs for c in cases])
     offs = np.concatenate([[0], np.cumsum([len(c.msgs) for c in cases])] +
-                          ([[len(msgs)]] if res == "tail" else [])).astype(np.int64)
+                          ([[len(msgs)]] if tail else [])).astype(np.int64)
     g = run_gpu(caps, msgs, offs, levels=3, l2_mode=lob.L2_FINAL, plan=RESIDENCY[res])
     for i, c in enumerate(cases):
         tr = g["trades"][g["trade_offs"][i]:g["trade_offs"][i + 1]]
@@ -126,8 +128,9 @@ def test_plans_agree_c0(plan):
     {"registers": 0, "lds_slots": 128},
     {"lds_slots": 200},
     {"layout": 1, "books_per_block": 2},
+    {"tail_shallow": 1},
 ], ids=["default", "spill128", "persistent", "split", "split_spill", "lds", "lds_spill128", "regs_tail200",
-        "unsorted"])
+        "unsorted", "tail_shallow"])
 def test_ragged_mixed_capacities(plan):
     """Capacities {50,100,500,1000} and uneven stream lengths in one call."""
     w = W.ragged(n_books=96, max_flow=4000)
@@ -142,7 +145,8 @@ def test_ragged_mixed_capacities(plan):
     {"ragged_split": 100, "lds_slots_big": 1000},
     {"ragged_split": 128, "lds_slots_big": 256, "books_per_block": 8, "books_per_block_big": 2},
     {"ragged_split": 64, "lds_slots_big": 64, "lds_slots": 64},
-], ids=["lpt_one_launch", "listed_order", "split_lds", "split_spill", "split_small_windows"])
+    {"ragged_split": 100, "lds_slots_big": 1000, "tail_shallow": 1},
+], ids=["lpt_one_launch", "listed_order", "split_lds", "split_spill", "split_small_windows", "split_tail_shallow"])
 def test_process_ragged(plan):
     """lob_process_ragged: longest stream first, capacity buckets on two streams."""
     w = W.ragged(n_books=96, max_flow=4000)
@@ -281,11 +285,13 @@ def test_extreme_capacities(group, plan):
     assert (o["stats"]["rejected_qty"] > 0).all() and (o["stats"]["cancel_miss"] > 0).all()
 
 
-def test_extreme_capacities_ragged():
+@pytest.mark.parametrize("shallow", [0, 1])
+def test_extreme_capacities_ragged(shallow):
     """Both groups in one lob_process_ragged call, split into a register bucket and
-    a register + tail bucket."""
+    a register + tail bucket (either code of the TAIL form)."""
     caps, msgs, offs = deep_streams([1, 2, 64, 128, 129, 1000, lob.MAX_CAPACITY], seed=13)
-    g = run_gpu(caps, msgs, offs, l2_mode=lob.L2_FINAL, plan={"ragged_split": 128}, ragged=True)
+    g = run_gpu(caps, msgs, offs, l2_mode=lob.L2_FINAL, plan={"ragged_split": 128, "tail_shallow": shallow},
+                ragged=True)
     o = run_oracle(caps, msgs, offs, l2_mode=O.L2_FINAL)
     assert_same(g, o, "extreme ragged")
 
