@@ -362,14 +362,16 @@ def bench_serving(args, n_books=20_000, lams=(50_000, 100_000, 200_000, 500_000)
     dev = torch.device("cuda:0")
     out = {"workload": f"{n_books} books, capacity {{50,100,500,1000}}, Poisson arrivals for "
                        f"{duration_s}s per rate, 50% replay / 50% step, 1..1000 msgs per request, "
-                       f"4 batch slots, 1 GiB staging budget", "rates": []}
+                       f"{args.serve_slots} batch slots of at most {args.serve_max_batch} requests, 1 GiB staging "
+                       f"budget", "rates": []}
     # untimed warm-up, a full run at the first rate: the first serving run in a
     # process shows a tail (p99 12-17 ms at 50k req/s against 1 ms on a second run)
     # that a 0.05 s warm-up did not remove
     sw = S.ServingWorkload(n_books, lams[0], duration_s, threads=host_cores())
     ctx = lob.Context(sw.caps, l2_levels=LEVELS, trade_log_records=2 * sw.caps.astype(np.int64) + 2 * 1004)
     ctx.set_plan(lds_slots=128, books_per_block=2)
-    srv = S.Server(ctx, n_slots=4, hbm_budget=1 << 30, max_batch=4096, max_request_msgs=1000, fill_cap=64)
+    srv = S.Server(ctx, n_slots=args.serve_slots, hbm_budget=1 << 30, max_batch=args.serve_max_batch,
+                       max_request_msgs=1000, fill_cap=64)
     srv.run(sw.requests(), sw.arrival)
     srv.close()
     ctx.close()
@@ -388,7 +390,8 @@ def bench_serving(args, n_books=20_000, lams=(50_000, 100_000, 200_000, 500_000)
         reqs = sw.requests()
         log(f"serving {lam / 1e3:.0f}k req/s: {sw.n} requests, {int(sw.size.sum())} msgs prepared in "
             f"{time.perf_counter() - t0:.1f}s")
-        srv = S.Server(ctx, n_slots=4, hbm_budget=1 << 30, max_batch=4096, max_request_msgs=1000, fill_cap=64)
+        srv = S.Server(ctx, n_slots=args.serve_slots, hbm_budget=1 << 30, max_batch=args.serve_max_batch,
+                       max_request_msgs=1000, fill_cap=64)
         comp = srv.run(reqs, sw.arrival)
         srv.close()
         lat = (comp["complete_ns"] - comp["arrival_ns"]) / 1e6
@@ -706,6 +709,8 @@ def main():
                     choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout", "occupancy"])
     ap.add_argument("--tune-trials", type=int, default=19)
     ap.add_argument("--graph-reps", type=int, default=2)
+    ap.add_argument("--serve-slots", type=int, default=4, help="serving: batches in flight")
+    ap.add_argument("--serve-max-batch", type=int, default=4096, help="serving: requests per batch at most")
     ap.add_argument("--step-chains", type=int, default=2,
                     help="step form: book groups stepping in independent chains inside the graph")
     ap.add_argument("--plan", default=None, help="JSON lob_plan fields")
