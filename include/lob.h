@@ -235,7 +235,8 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
  * from empty books: the listed ids are checked (LOB_EINVAL if one is out of range,
  * before anything runs) and the listed books reset before each run and left reset
  * at the end (their previous state is lost).  At most max_trials candidates (>= 1),
- * four runs each; a candidate that does not fit (LDS) is skipped and not counted.
+ * four runs each (one when the untimed run already takes twice the best time so
+ * far); a candidate that does not fit (LDS) is skipped and not counted.
  * Waits for the device (not graph-capturable). */
 lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books,
                                const int32_t *msgs, const int64_t *msg_offsets_host,

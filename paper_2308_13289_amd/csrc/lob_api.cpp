@@ -589,9 +589,18 @@ lob_status lob_autotune_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32
     if (trials >= max_trials) return LOB_OK;
     if (lob_set_plan(ctx, &p) != LOB_OK) return LOB_OK;  // candidate does not fit: skip it
     ++trials;
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(ctx, LOB_EDEVICE, "autotune event");
     lob_status r = lob_process_ragged(ctx, book_ids_host, n_books, msgs, msg_offsets_host, LOB_L2_NONE, nullptr,
                                       stream);  // stages the schedule; warms caches
     if (r != LOB_OK) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(ctx, LOB_EDEVICE, "autotune sync");
+    {
+      // a candidate whose untimed run already took twice the best time is not run again
+      float ms0 = 0.f;
+      (void)hipEventElapsedTime(&ms0, e0, e1);
+      if (ms0 > 2.f * best_t) return reset_listed();
+    }
     float t[3];
     for (float &ms : t) {
       if ((r = reset_listed()) != LOB_OK) return r;
