@@ -92,6 +92,25 @@ class StepRunner:
             self.ctx.step(self.win[s], self.l2[s], actions=self.act[s], agent_tid=AGENT,
                           fills=self.fills[s], fill_counts=self.counts[s])
 
+    def run_steps_two_chains(self, side):
+        """The steps of each half of the books as a chain of launches on its own
+        stream (the first half on the current stream, the second on `side`)."""
+        cur = torch.cuda.current_stream()
+        half = self.n // 2
+        ids = [torch.arange(0, half, dtype=torch.int32, device="cuda:0"),
+               torch.arange(half, self.n, dtype=torch.int32, device="cuda:0")]
+        fork = torch.cuda.Event()
+        fork.record(cur)
+        side.wait_event(fork)
+        for s in range(self.steps):
+            for c, (lo, hi, st) in enumerate(((0, half, cur), (half, self.n, side))):
+                self.ctx.step(self.win[s][lo:hi], self.l2[s, lo:hi], actions=self.act[s][lo:hi], book_ids=ids[c],
+                              agent_tid=AGENT, fills=self.fills[s, lo:hi], fill_counts=self.counts[s, lo:hi],
+                              stream=st)
+        join = torch.cuda.Event()
+        join.record(side)
+        cur.wait_event(join)
+
     def outputs(self):
         torch.cuda.synchronize()
         return self.l2.cpu().numpy().copy(), self.fills.cpu().numpy().copy(), self.counts.cpu().numpy().copy()
@@ -157,6 +176,36 @@ def test_step_graph_replays_match_eager():
         R.run_steps()
     for rep in range(3):
         R.seed()                     # eager work between replays
+        R.l2.zero_()
+        R.fills.zero_()
+        R.counts.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        got = R.outputs()
+        for a, b in zip(got, eager):
+            np.testing.assert_array_equal(a, b, err_msg=f"replay {rep}")
+
+
+def test_step_graph_of_two_chains_matches_eager():
+    """The graph as the benchmark builds it: the two halves of the books step in two
+    chains of launches on two streams.  Every replay (eager work between them)
+    equals the eager run of all books together and the oracle."""
+    w, seed_blk, windows, actions = step_case(32, 12)
+    F = 64
+    R = StepRunner(w.caps, seed_blk, windows, actions, F=F)
+    R.seed()
+    R.run_steps()
+    eager = R.outputs()
+    ol2, ofills = oracle_steps(w.caps, seed_blk, windows, actions)
+    check_against_oracle(*eager, ol2, ofills, F)
+    side = torch.cuda.Stream()
+    R.seed()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        R.run_steps_two_chains(side)
+    for rep in range(3):
+        R.seed()
         R.l2.zero_()
         R.fills.zero_()
         R.counts.zero_()
