@@ -548,6 +548,63 @@ def bench_step(args, n_books=8192, n_steps=1000, window=100, fills_cap=32):
     return res
 
 
+def bench_exec(args, n_books=8192, n_steps=200, window=100, F=64):
+    """Execution-environment steps (Section 5.2; lob_exec_step): 8192 books of
+    capacity 100 seeded with 100 orders, each with a buy or sell task of 300-2000
+    shares; per step a 100-message data window, the agent's four-level action (a
+    random size per level), the matcher with per-message level-1 rows, and the
+    observation vector and reward.  Eager steps, timed one by one with HIP events."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    w = W.uniform(n_books, window * n_steps, cap=100, tag=W.TAGS["c3"], threads=host_cores(),
+                  name=f"exec{n_books}x{window * n_steps}c100")
+    seeds = 100
+    per = seeds + window * n_steps
+    d_all = torch.from_numpy(w.msgs).to(dev).view(n_books, per, 8)
+    ctx = lob.Context(w.caps, l2_levels=LEVELS, trade_log_records=np.full(n_books, 2 * (window + 4) + 8))
+    ctx.process(d_all[:, :seeds].contiguous().view(-1, 8),
+                torch.arange(n_books + 1, dtype=torch.int64, device=dev) * seeds, stream=stream)
+    l2 = ctx.read_l2(stream=stream).cpu().numpy()  # [n][2][L][2]: the seeded books' best prices
+    rng = np.random.default_rng(11)
+    state = np.zeros(n_books, lob.EXEC_STATE_DTYPE)
+    state["task_side"] = np.where(np.arange(n_books) % 2 == 1, 1, -1)
+    state["task_qty"] = rng.integers(300, 2000, n_books)
+    state["p_init"] = (l2[:, 0, 0, 0].astype(np.int64) + l2[:, 1, 0, 0]) // 2
+    start = w.msgs.reshape(n_books, per, 8)[:, seeds, 6:8]
+    state["start_s"], state["start_ns"] = start[:, 0], start[:, 1]
+    state["end_s"] = start[:, 0] + 1_000_000  # no forced market order within the timed steps
+    state["next_oid"] = 1_000_000_000
+    d_state = torch.from_numpy(state.view(np.uint8)).to(dev)
+    d_win = d_all[:, seeds:].reshape(n_books, n_steps, window, 8).permute(1, 0, 2, 3).contiguous()
+    del d_all
+    d_act = torch.from_numpy(rng.integers(-20, 60, (n_steps, n_books, 4)).astype(np.int32)).to(dev)
+    obs = torch.zeros((n_books, 6 * window + 8), dtype=torch.int32, device=dev)
+    reward = torch.zeros(n_books, dtype=torch.float64, device=dev)
+    fills = torch.zeros((n_books, F, 6), dtype=torch.int32, device=dev)
+    counts = torch.zeros(n_books, dtype=torch.int32, device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(n_steps):
+        ev[s][0].record(stream)
+        ctx.exec_step(d_win[s], d_act[s], d_state, obs, reward, fills, counts, tick=100, passive_ticks=2,
+                      agent_tid=-1, lam=0.3, stream=stream)
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    st = d_state.cpu().numpy().view(lob.EXEC_STATE_DTYPE)
+    res = {"workload": f"{n_books} books x {n_steps} execution steps x ({window} data msgs + the agent's "
+                       f"orders), capacity 100, observation + reward per step",
+           "steps_per_s": n_steps / wall, "msgs_per_s": n_books * n_steps * window / wall,
+           "step_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
+                       "mean": float(ms.mean())},
+           "agent_executed_qty": int(st["exec_qty"].sum()), "tasks_done": int(st["done"].sum()),
+           "flags": int(np.bitwise_or.reduce(st["flags"]))}
+    ctx.close()
+    return res
+
+
 def _time_plan(w, plan, reps, warmup=1):
     """msgs/s of one plain process launch over workload w with the given plan (books
     reset before every launch, final L2), plus a bit-exact spot check."""
@@ -706,7 +763,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout", "occupancy"])
+                    choices=["all", "c1", "c0", "c2", "c3", "c4", "copy", "micro", "layout", "occupancy", "exec"])
     ap.add_argument("--tune-trials", type=int, default=19)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--serve-slots", type=int, default=4, help="serving: batches in flight")
@@ -745,6 +802,9 @@ def main():
     if args.workload == "occupancy":
         print(json.dumps(bench_occupancy(args)), flush=True)
         return
+    if args.workload == "exec":
+        print(json.dumps(bench_exec(args)), flush=True)
+        return
     t0 = time.perf_counter()
     if args.workload in ("c1", "all"):
         w = W.c1(threads=host_cores())
@@ -768,6 +828,9 @@ def main():
         log(f"step form: {res['step_form']['steps_per_s']:.0f} steps/s, "
             f"p99 {res['step_form']['eager_step_ms']['p99']:.3f} ms")
         res["serving"] = bench_serving(args)
+        res["exec_env"] = bench_exec(args)
+        log(f"execution env: {res['exec_env']['steps_per_s']:.0f} steps/s, "
+            f"p99 {res['exec_env']['step_ms']['p99']:.3f} ms")
         res["layout_ablation"] = bench_layout(args, reps=2)
         log("layout ablation (C1 msgs/s): " + ", ".join(
             f"{r['plan']}: {r['msgs_per_s'] / 1e9:.2f} G" for r in res["layout_ablation"]["c1_4096x10100_cap100"]))
