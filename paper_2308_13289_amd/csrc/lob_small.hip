@@ -904,6 +904,38 @@ __device__ __forceinline__ void write_l2(const Book &bk, const RState &st, int L
   l2_side<TAIL>(bk.bid, bk.tl[1], st.n[1], L, o + L);
 }
 
+// write_l2 with L = 1 (the per-message rows of the execution environment): each
+// side's best price and the exact quantity resting at it, min(sum, INT_MAX).  A side
+// is sorted by price, so the best level is every slot holding slot 0's price; lane l
+// adds its two register slots (l and 64 + l) and one saturating scan per side sums
+// the lanes (saturating adds of non-negative values give min(sum, INT_MAX) in any
+// order), the two sides' scans independent of each other.  With a tail, a level that
+// goes on past slot 127 takes the general form.
+__device__ __forceinline__ int l1_lane_qty(const Side &S, int n, int p0) {
+  const int l = lane_id();
+  const int x = l < n && S.c0.p == p0 ? S.c0.q : 0;
+  const int y = l + kWave < n && S.c1.p == p0 ? S.c1.q : 0;
+  return sat_add(x, y);
+}
+
+template <bool TAIL>
+__device__ __forceinline__ void write_l1(const Book &bk, const RState &st, int32_t *row) {
+  const int l = lane_id();
+  const int na = st.n[0], nb = st.n[1];
+  const int pa = rdlane(bk.ask.c0.p, 0), pb = rdlane(bk.bid.c0.p, 0);
+  if constexpr (TAIL) {
+    if (LOB_UNLIKELY((na > kSlots && rdlane(bk.ask.c1.p, kWave - 1) == pa) ||
+                     (nb > kSlots && rdlane(bk.bid.c1.p, kWave - 1) == pb))) {
+      write_l2<TAIL>(bk, st, 1, row);
+      return;
+    }
+  }
+  const int sa = scan_incl_sat(l1_lane_qty(bk.ask, na, pa));
+  const int sb = scan_incl_sat(l1_lane_qty(bk.bid, nb, pb));
+  const int qa = rdlane(sa, kWave - 1), qb = rdlane(sb, kWave - 1);
+  if (l < 4) row[l] = l == 0 ? (na > 0 ? pa : -1) : l == 1 ? qa : l == 2 ? (nb > 0 ? pb : -1) : qb;
+}
+
 // Handle of the order added by message k (j of the chunk v): 2k, plus 1 when the
 // launch collects agent fills and the message carries the agent's trader id.
 template <bool TAIL, int X>
@@ -1043,7 +1075,12 @@ __device__ __forceinline__ bool process_all(Book &bk, RState &st, Stage &sg, con
           c = rdlane(code, j);
         process_msg<TAIL, X, false>(bk, st, sg, c, u, v, j, (int)k0 + j, pk);
         if constexpr ((X & 2) != 0) {
-          if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+          if (l2_rows && j < c1) {
+            if constexpr ((X & 16) != 0)
+              write_l1<TAIL>(bk, st, l2_rows + (k0 + j) * 4);
+            else
+              write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
+          }
         }
         if constexpr (kReadAhead<TAIL, X>) c = cn;
       }
@@ -1383,12 +1420,14 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int grid = (a.n + a.bpb - 1) / a.bpb;
   const size_t lds = tail ? (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2) : 0;
   // X: bit 0 agent fills, bit 1 per-message L2, bit 2 rotating priorities (without a
-  // tail only), bit 3 the TAIL form's chunk-0 insert (kChunk0Insert; alone only)
+  // tail only), bit 3 the TAIL form's chunk-0 insert (kChunk0Insert; alone only),
+  // bit 4 per-message rows of level 1 (with agent fills: the execution step)
   int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0) | (!tail && a.rotate ? 4 : 0);
   if (tail && x == 0 && a.tail_shallow) x = 8;
-  switch ((tail ? 16 : 0) | x) {
+  if ((x & 3) == 3 && a.levels == 1) x |= 16;
+  switch ((tail ? 32 : 0) | x) {
 #define LOB_SMALL_CASE(T, X)                                                                   \
-  case (T ? 16 : 0) | X:                                                                       \
+  case (T ? 32 : 0) | X:                                                                       \
     hipLaunchKernelGGL((k_process_small<T, X>), dim3(grid), dim3(threads), T ? lds : 0, s, a); \
     break;
     LOB_SMALL_CASE(false, 0)
@@ -1399,10 +1438,13 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
     LOB_SMALL_CASE(false, 5)
     LOB_SMALL_CASE(false, 6)
     LOB_SMALL_CASE(false, 7)
+    LOB_SMALL_CASE(false, 19)
+    LOB_SMALL_CASE(false, 23)
     LOB_SMALL_CASE(true, 0)
     LOB_SMALL_CASE(true, 1)
     LOB_SMALL_CASE(true, 2)
     LOB_SMALL_CASE(true, 3)
+    LOB_SMALL_CASE(true, 19)
     LOB_SMALL_CASE(true, 8)
 #undef LOB_SMALL_CASE
   }
@@ -1410,9 +1452,9 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
 }
 
 hipError_t set_process_small_lds_limit(size_t bytes) {
-  const void *k[5] = {(const void *)k_process_small<true, 0>, (const void *)k_process_small<true, 1>,
+  const void *k[6] = {(const void *)k_process_small<true, 0>, (const void *)k_process_small<true, 1>,
                       (const void *)k_process_small<true, 2>, (const void *)k_process_small<true, 3>,
-                      (const void *)k_process_small<true, 8>};
+                      (const void *)k_process_small<true, 8>, (const void *)k_process_small<true, 19>};
   for (const void *f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;

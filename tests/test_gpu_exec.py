@@ -165,3 +165,111 @@ def test_exec_step_more_fills_than_buffer(res, F):
                 assert (gs["exec_qty"], gs["revenue"], gs["done"]) == (env.exec_qty, env.revenue, env.done), i
                 assert g_obs[i, -1] == o_obs[-1] and g_rew[i] == o_rew, (step, i)
     assert flagged == (n_books // 2 if F == 8 else 0)
+
+
+def deep_level_books(cap, depths, rng):
+    """Seeds and flow for books whose best level holds d orders on each side (d up to
+    the capacity); one side's orders of 2^29 shares (4 or more sum past INT32_MAX), the
+    other's of about a thousand, alternating by book.  The flow cancels best-level
+    orders (in part or whole), adds to the best levels, trades against them and rests
+    one tick behind them, so depth, sum and price of level 1 change message by message."""
+    big = 1 << 29
+    pa, pb = 1_000_000, 990_000
+    seeds, flows = [], []
+    for i, d in enumerate(depths):
+        t = [34200, 0]
+
+        def tick():
+            t[1] += 1
+            return list(t)
+        qs = {-1: big, 1: 1000} if i % 2 == 0 else {-1: 1000, 1: big}
+        book, oids = [], {-1: [], 1: []}
+        for sd, p0, step in ((-1, pa, 100), (1, pb, -100)):
+            for k in range(d):
+                oid = 10_000 * (2 + sd) + k
+                oids[sd].append(oid)
+                book.append([1, sd, p0, qs[sd] + (k % 7), oid, 7] + tick())
+            for k in range(min(cap - d, 3)):
+                book.append([1, sd, p0 + step * (k + 1), qs[sd], 50_000 + 10 * (2 + sd) + k, 7] + tick())
+        flow = []
+        next_oid = 100_000
+        for _ in range(3 * 60):
+            sd = int(rng.choice([-1, 1]))
+            p0 = pa if sd == -1 else pb
+            r = rng.random()
+            if r < 0.35:
+                oid = int(rng.choice(oids[sd]))
+                flow.append([2 if rng.random() < 0.5 else 3, sd, p0, int(rng.choice([100, 1 << 30])), oid, 7] + tick())
+            elif r < 0.6:
+                flow.append([1, sd, p0, qs[sd], next_oid, 7] + tick())
+                oids[sd].append(next_oid)
+                next_oid += 1
+            elif r < 0.8:
+                flow.append([4, -sd, 0, int(0.6 * qs[sd]), next_oid, 7] + tick())
+                next_oid += 1
+            else:
+                flow.append([1, sd, p0 + (100 if sd == -1 else -100), qs[sd], next_oid, 7] + tick())
+                next_oid += 1
+        seeds.append(np.array(book, np.int32))
+        flows.append(np.array(flow, np.int32))
+    return seeds, np.stack(flows)
+
+
+@pytest.mark.parametrize("res", [{"registers": 1}, {"registers": 0}])
+@pytest.mark.parametrize("cap", [100, 128, 250])
+def test_exec_step_deep_best_level(res, cap):
+    """Level-1 rows when the best level holds from 1 order to the whole capacity: a
+    level spanning both register chunks and, at capacity 250, the tail; level sums past
+    INT32_MAX saturate.  Observation, reward, task state and books equal the oracle's
+    after every step (three steps of 60 data messages, no agent orders)."""
+    depths = sorted({d for d in (1, 2, 3, 63, 64, 65, 127, 128, 129, 200) if d <= cap} | {cap})
+    n_books, Wn, F = len(depths), 60, 16
+    rng = np.random.default_rng(cap)
+    seeds, flow = deep_level_books(cap, depths, rng)
+    ctx = lob.Context(np.full(n_books, cap, np.int32), l2_levels=1,
+                      trade_log_records=np.full(n_books, 4 * Wn + 2 * cap + 8))
+    ctx.set_plan(**res)
+    offs = np.concatenate([[0], np.cumsum([len(s) for s in seeds])]).astype(np.int64)
+    ctx.process(to_dev(np.concatenate(seeds)), to_dev(offs))
+    state = np.zeros(n_books, lob.EXEC_STATE_DTYPE)
+    envs = []
+    for i in range(n_books):
+        b = O.Book(cap)
+        for m in seeds[i]:
+            b.process(m)
+        s = state[i]
+        s["task_side"] = 1 if i % 2 else -1
+        s["task_qty"] = 1000
+        s["p_init"] = 995_000
+        s["start_s"], s["start_ns"] = 34200, 0
+        s["end_s"] = 40000
+        s["next_oid"] = 1_000_000
+        envs.append(ExecEnv(b, s["task_side"], s["task_qty"], s["p_init"], (34200, 0), s["end_s"], s["next_oid"],
+                            tick=100, passive_ticks=2, agent_tid=AGENT, lam=0.3))
+    d_state = torch.from_numpy(state.view(np.uint8)).cuda()
+    obs = torch.zeros((n_books, 6 * Wn + 8), dtype=torch.int32, device="cuda:0")
+    reward = torch.zeros(n_books, dtype=torch.float64, device="cuda:0")
+    fills = torch.zeros((n_books, F, 6), dtype=torch.int32, device="cuda:0")
+    counts = torch.zeros(n_books, dtype=torch.int32, device="cuda:0")
+    act = np.zeros((n_books, 4), np.int32)
+    saturated = 0
+    for k in range(3):
+        win = np.ascontiguousarray(flow[:, k * Wn:(k + 1) * Wn])
+        ctx.exec_step(to_dev(win), to_dev(act), d_state, obs, reward, fills, counts, tick=100, passive_ticks=2,
+                      agent_tid=AGENT, lam=0.3)
+        g_obs, g_rew = obs.cpu().numpy(), reward.cpu().numpy()
+        g_state = d_state.cpu().numpy().view(lob.EXEC_STATE_DTYPE)
+        for i, env in enumerate(envs):
+            o_obs, o_rew, _ = env.step(win[i], act[i])
+            saturated += int((np.abs(o_obs[5 * Wn:6 * Wn].astype(np.int64)) >= (1 << 31) - (1 << 20)).sum())
+            np.testing.assert_array_equal(g_obs[i], o_obs, err_msg=f"obs book {i} (depth {depths[i]}) step {k}")
+            assert g_rew[i] == o_rew, (i, k)
+            gs = g_state[i]
+            assert (gs["exec_qty"], gs["revenue"], gs["done"], gs["flags"]) == \
+                (env.exec_qty, env.revenue, env.done, 0), (i, k)
+    assert saturated > 0
+    dump = ctx.read_book(cap).cpu().numpy()
+    for i, env in enumerate(envs):
+        for sd in (0, 1):
+            want = env.book.dump(sd)
+            np.testing.assert_array_equal(dump[i, sd, :len(want)], want, err_msg=f"book {i} side {sd}")
