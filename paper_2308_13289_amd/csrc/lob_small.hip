@@ -909,8 +909,9 @@ __device__ __forceinline__ void write_l2(const Book &bk, const RState &st, int L
 // is sorted by price, so the best level is every slot holding slot 0's price; lane l
 // adds its two register slots (l and 64 + l) and one saturating scan per side sums
 // the lanes (saturating adds of non-negative values give min(sum, INT_MAX) in any
-// order), the two sides' scans independent of each other.  With a tail, a level that
-// goes on past slot 127 takes the general form.
+// order), the two sides' scans independent of each other; when neither best price
+// has a second order, slot 0's quantities are the sums and the scans are skipped.
+// With a tail, a level that goes on past slot 127 takes the general form.
 __device__ __forceinline__ int l1_lane_qty(const Side &S, int n, int p0) {
   const int l = lane_id();
   const int x = l < n && S.c0.p == p0 ? S.c0.q : 0;
@@ -930,9 +931,17 @@ __device__ __forceinline__ void write_l1(const Book &bk, const RState &st, int32
       return;
     }
   }
-  const int sa = scan_incl_sat(l1_lane_qty(bk.ask, na, pa));
-  const int sb = scan_incl_sat(l1_lane_qty(bk.bid, nb, pb));
-  const int qa = rdlane(sa, kWave - 1), qb = rdlane(sb, kWave - 1);
+  int qa, qb;
+  if (LOB_LIKELY((na <= 1 || rdlane(bk.ask.c0.p, 1) != pa) && (nb <= 1 || rdlane(bk.bid.c0.p, 1) != pb))) {
+    // the common case: at most one order at each best price
+    qa = na > 0 ? rdlane(bk.ask.c0.q, 0) : 0;
+    qb = nb > 0 ? rdlane(bk.bid.c0.q, 0) : 0;
+  } else {
+    const int sa = scan_incl_sat(l1_lane_qty(bk.ask, na, pa));
+    const int sb = scan_incl_sat(l1_lane_qty(bk.bid, nb, pb));
+    qa = rdlane(sa, kWave - 1);
+    qb = rdlane(sb, kWave - 1);
+  }
   if (l < 4) row[l] = l == 0 ? (na > 0 ? pa : -1) : l == 1 ? qa : l == 2 ? (nb > 0 ? pb : -1) : qb;
 }
 
