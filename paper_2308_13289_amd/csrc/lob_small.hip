@@ -931,18 +931,27 @@ __device__ __forceinline__ void write_l1(const Book &bk, const RState &st, int32
       return;
     }
   }
+  // lane 1 of a side of one order holds a stale price: the count decides first
+  const int pa1 = rdlane(bk.ask.c0.p, 1), pb1 = rdlane(bk.bid.c0.p, 1);
+  const int qa0 = rdlane(bk.ask.c0.q, 0), qb0 = rdlane(bk.bid.c0.q, 0);
   int qa, qb;
-  if (LOB_LIKELY((na <= 1 || rdlane(bk.ask.c0.p, 1) != pa) && (nb <= 1 || rdlane(bk.bid.c0.p, 1) != pb))) {
+  if (LOB_LIKELY((na <= 1 || pa1 != pa) && (nb <= 1 || pb1 != pb))) {
     // the common case: at most one order at each best price
-    qa = na > 0 ? rdlane(bk.ask.c0.q, 0) : 0;
-    qb = nb > 0 ? rdlane(bk.bid.c0.q, 0) : 0;
+    qa = na > 0 ? qa0 : 0;
+    qb = nb > 0 ? qb0 : 0;
   } else {
     const int sa = scan_incl_sat(l1_lane_qty(bk.ask, na, pa));
     const int sb = scan_incl_sat(l1_lane_qty(bk.bid, nb, pb));
     qa = rdlane(sa, kWave - 1);
     qb = rdlane(sb, kWave - 1);
   }
-  if (l < 4) row[l] = l == 0 ? (na > 0 ? pa : -1) : l == 1 ? qa : l == 2 ? (nb > 0 ? pb : -1) : qb;
+  // the row in lanes 0-3 by lane writes: no lane-dependent selects, which the compiler
+  // lays out as branches under exec masks
+  int r = wl(0, na > 0 ? pa : -1, 0);
+  r = wl(r, qa, 1);
+  r = wl(r, nb > 0 ? pb : -1, 2);
+  r = wl(r, qb, 3);
+  if (l < 4) row[l] = r;
 }
 
 // Handle of the order added by message k (j of the chunk v): 2k, plus 1 when the
