@@ -905,7 +905,9 @@ __device__ __forceinline__ void write_l2(const Book &bk, const RState &st, int L
 }
 
 // write_l2 with L = 1 (the per-message rows of the execution environment): each
-// side's best price and the exact quantity resting at it, min(sum, INT_MAX).  A side
+// side's best price and the exact quantity resting at it, min(sum, INT_MAX); an empty
+// side has quantity 0 and an unspecified price (the execution step tells the sides
+// apart by quantity).  A side
 // is sorted by price, so the best level is every slot holding slot 0's price; lane l
 // adds its two register slots (l and 64 + l) and one saturating scan per side sums
 // the lanes (saturating adds of non-negative values give min(sum, INT_MAX) in any
@@ -947,9 +949,9 @@ __device__ __forceinline__ void write_l1(const Book &bk, const RState &st, int32
   }
   // the row in lanes 0-3 by lane writes: no lane-dependent selects, which the compiler
   // lays out as branches under exec masks
-  int r = wl(0, na > 0 ? pa : -1, 0);
+  int r = wl(0, pa, 0);
   r = wl(r, qa, 1);
-  r = wl(r, nb > 0 ? pb : -1, 2);
+  r = wl(r, pb, 2);
   r = wl(r, qb, 3);
   if (l < 4) row[l] = r;
 }
@@ -1092,13 +1094,10 @@ __device__ __forceinline__ bool process_all(Book &bk, RState &st, Stage &sg, con
         else
           c = rdlane(code, j);
         process_msg<TAIL, X, false>(bk, st, sg, c, u, v, j, (int)k0 + j, pk);
-        if constexpr ((X & 2) != 0) {
-          if (l2_rows && j < c1) {
-            if constexpr ((X & 16) != 0)
-              write_l1<TAIL>(bk, st, l2_rows + (k0 + j) * 4);
-            else
-              write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
-          }
+        if constexpr ((X & 16) != 0) {
+          if (j < c1) write_l1<TAIL>(bk, st, l2_rows + (k0 + j) * 4);  // (the host gives X bit 4 rows)
+        } else if constexpr ((X & 2) != 0) {
+          if (l2_rows && j < c1) write_l2<TAIL>(bk, st, a.levels, l2_rows + (k0 + j) * 4 * a.levels);
         }
         if constexpr (kReadAhead<TAIL, X>) c = cn;
       }
@@ -1442,7 +1441,7 @@ hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   // bit 4 per-message rows of level 1 (with agent fills: the execution step)
   int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0) | (!tail && a.rotate ? 4 : 0);
   if (tail && x == 0 && a.tail_shallow) x = 8;
-  if ((x & 3) == 3 && a.levels == 1) x |= 16;
+  if ((x & 3) == 3 && a.levels == 1 && a.l2_out != nullptr) x |= 16;
   switch ((tail ? 32 : 0) | x) {
 #define LOB_SMALL_CASE(T, X)                                                                   \
   case (T ? 32 : 0) | X:                                                                       \
