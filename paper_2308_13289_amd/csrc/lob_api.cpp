@@ -462,6 +462,41 @@ static lob_status stage_copy(lob_ctx *ctx, size_t bytes, hipStream_t s) {
   return LOB_OK;
 }
 
+// v (list positions in increasing order) sorted by decreasing stream length, equal
+// lengths in increasing position: a stable least-significant-digit radix sort of
+// (longest - length), 11 bits per pass (two passes for streams below 4M messages).
+// The host does this before every ragged launch while the GPU waits, so it is kept
+// linear: a comparison sort of 10,000 books took about 0.5 ms.
+static void sort_longest_first(std::vector<int32_t> &v, const int64_t *offs) {
+  const size_t n = v.size();
+  if (n < 2) return;
+  int64_t longest = 0;
+  for (int32_t i : v) longest = std::max<int64_t>(longest, offs[i + 1] - offs[i]);
+  std::vector<uint64_t> key(n), key2(n);
+  std::vector<int32_t> v2(n);
+  for (size_t k = 0; k < n; ++k) key[k] = (uint64_t)(longest - (offs[v[k] + 1] - offs[v[k]]));
+  constexpr int kBits = 11;
+  constexpr uint64_t kMask = (1u << kBits) - 1;
+  std::vector<uint32_t> count((size_t)1 << kBits);
+  for (int shift = 0; shift < 64 && ((uint64_t)longest >> shift) != 0; shift += kBits) {
+    std::fill(count.begin(), count.end(), 0u);
+    for (size_t k = 0; k < n; ++k) ++count[(key[k] >> shift) & kMask];
+    uint32_t sum = 0;
+    for (uint32_t &c : count) {
+      const uint32_t t = c;
+      c = sum;
+      sum += t;
+    }
+    for (size_t k = 0; k < n; ++k) {
+      const uint32_t at = count[(key[k] >> shift) & kMask]++;
+      key2[at] = key[k];
+      v2[at] = v[k];
+    }
+    key.swap(key2);
+    v.swap(v2);
+  }
+}
+
 lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_t n_books, const int32_t *msgs,
                               const int64_t *msg_offsets_host, int32_t l2_mode, int32_t *l2_out, void *stream) {
   lob_status st = check_list(ctx, n_books);
@@ -489,9 +524,8 @@ lob_status lob_process_ragged(lob_ctx *ctx, const int32_t *book_ids_host, int32_
   }
   auto len = [&](int32_t i) { return msg_offsets_host[i + 1] - msg_offsets_host[i]; };
   if (p.ragged_order) {
-    auto longest_first = [&](int32_t x, int32_t y) { return len(x) != len(y) ? len(x) > len(y) : x < y; };
-    std::sort(small.begin(), small.end(), longest_first);
-    std::sort(big.begin(), big.end(), longest_first);
+    sort_longest_first(small, msg_offsets_host);
+    sort_longest_first(big, msg_offsets_host);
   }
   // stage [ids | rows | ranges] in pinned memory, one copy to the device
   DeviceGuard g(ctx->device);
