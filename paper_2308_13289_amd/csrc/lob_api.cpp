@@ -153,8 +153,9 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
     hipError_t e = lob::launch_process_unsorted(a, s);
     return e == hipSuccess ? LOB_OK : hip_fail(c, e, "process launch");
   }
-  // the register kernel's forms with a tail or per-message L2 leave a book whose
-  // times go backwards to the LDS engine, launched right after them
+  // the register kernel's forms with a tail or per-message L2 (but the execution
+  // step's level-1 rows) leave a book whose times go backwards to the LDS engine,
+  // launched right after them
   auto deferred = [&](lob::ProcArgs b) -> lob_status {
     hipError_t e = lob::launch_process_deferred(b, std::min(cap_limit, 64), s);
     return e == hipSuccess ? LOB_OK : hip_fail(c, e, "deferred launch");
@@ -164,7 +165,7 @@ lob_status launch(lob_ctx *c, lob::ProcArgs a, int window, int cap_limit, int bp
       a.bpb = std::max(1, std::min(16, bpb));
       hipError_t e = lob::launch_process_small(a, false, s);
       if (e != hipSuccess) return hip_fail(c, e, "process launch");
-      return a.l2_mode == 1 ? deferred(a) : LOB_OK;
+      return lob::small_defers(a, false) ? deferred(a) : LOB_OK;
     }
     // the first 128 orders per side in registers, the rest in an LDS tail of
     // 16-byte entries (P, Q, OID, handle), tw per side

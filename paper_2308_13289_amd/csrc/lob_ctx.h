@@ -35,6 +35,8 @@ hipError_t launch_exec_finish(BookHdr *hdr, const int32_t *ids, int n, int n_tot
 hipError_t launch_seed_l2(BookHdr *hdr, int2 *books, const int32_t *ids, int n, int n_total, int L,
                           const int32_t *l2, const int32_t *times, int tid, hipStream_t s);
 hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s);
+// Whether that launch leaves books whose times go backwards to k_process_deferred.
+bool small_defers(const ProcArgs &a, bool tail);
 hipError_t set_process_small_lds_limit(size_t bytes);
 hipError_t launch_process_unsorted(const ProcArgs &a, hipStream_t s);
 hipError_t set_process_unsorted_lds_limit(size_t bytes);

@@ -179,13 +179,14 @@ template <bool TAIL, int X>
 constexpr bool kAgentMask = !TAIL && (X & 2) == 0;
 
 // Books whose times go backwards (Section 4.1: among equal prices the earlier time
-// has priority, which then differs from arrival order).  Without a tail and without
-// per-message L2, the kernel carries a second copy of its message loop whose insert
-// compares times (kTimedInline); the other forms leave such a book uncommitted and
-// mark it for the LDS engine, launched after them (k_process_deferred), which keeps
-// each order's time beside it.  Either way the hot loop holds no code for it.
+// has priority, which then differs from arrival order).  Without a tail, and without
+// per-message L2 or with the level-1 rows of the execution step, the kernel carries
+// a second copy of its message loop whose insert compares times (kTimedInline); the
+// other forms leave such a book uncommitted and mark it for the LDS engine, launched
+// after them (k_process_deferred, small_defers), which keeps each order's time
+// beside it.  Either way the hot loop holds no code for it.
 template <bool TAIL, int X>
-constexpr bool kTimedInline = !TAIL && (X & 2) == 0;
+constexpr bool kTimedInline = !TAIL && ((X & 2) == 0 || (X & 16) != 0);
 
 // The next message's case read one message ahead, off the dispatch's dependency
 // chain, for two more scalar moves per message: faster where few waves share a SIMD
@@ -1107,6 +1108,9 @@ __device__ __forceinline__ bool process_all(Book &bk, RState &st, Stage &sg, con
       for (int j = 0; j < cnt; ++j) {
         const int c = rdlane(code, j);
         process_msg<TAIL, X, true>(bk, st, sg, c, u, v, j, (int)k0 + j, pk);
+        if constexpr ((X & 16) != 0) {
+          if (j < c1) write_l1<TAIL>(bk, st, l2_rows + (k0 + j) * 4);
+        }
       }
     } else {
       return true;
@@ -1432,16 +1436,27 @@ int small_book_slots() { return kSlots; }
 
 // tail = false: books of capacity <= 128; tail = true: a.W tail entries per side in
 // LDS (a.lds_int2_per_wave = 4 * a.W per wave)
+// X of the instantiation a launch runs: bit 0 agent fills, bit 1 per-message L2, bit
+// 2 rotating priorities (without a tail only), bit 3 the TAIL form's chunk-0 insert
+// (kChunk0Insert; alone only), bit 4 per-message rows of level 1 (with agent fills:
+// the execution step)
+static int small_form(const ProcArgs &a, bool tail) {
+  int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0) | (!tail && a.rotate ? 4 : 0);
+  if (tail && x == 0 && a.tail_shallow) x = 8;
+  if ((x & 3) == 3 && a.levels == 1 && a.l2_out != nullptr) x |= 16;
+  return x;
+}
+
+bool small_defers(const ProcArgs &a, bool tail) {
+  const int x = small_form(a, tail);
+  return tail || ((x & 2) != 0 && (x & 16) == 0);  // not kTimedInline
+}
+
 hipError_t launch_process_small(const ProcArgs &a, bool tail, hipStream_t s) {
   const int threads = a.bpb * kWave;
   const int grid = (a.n + a.bpb - 1) / a.bpb;
   const size_t lds = tail ? (size_t)a.bpb * a.lds_int2_per_wave * sizeof(int2) : 0;
-  // X: bit 0 agent fills, bit 1 per-message L2, bit 2 rotating priorities (without a
-  // tail only), bit 3 the TAIL form's chunk-0 insert (kChunk0Insert; alone only),
-  // bit 4 per-message rows of level 1 (with agent fills: the execution step)
-  int x = (a.fills != nullptr ? 1 : 0) | (a.l2_mode == 1 ? 2 : 0) | (!tail && a.rotate ? 4 : 0);
-  if (tail && x == 0 && a.tail_shallow) x = 8;
-  if ((x & 3) == 3 && a.levels == 1 && a.l2_out != nullptr) x |= 16;
+  const int x = small_form(a, tail);
   switch ((tail ? 32 : 0) | x) {
 #define LOB_SMALL_CASE(T, X)                                                                   \
   case (T ? 32 : 0) | X:                                                                       \

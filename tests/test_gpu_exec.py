@@ -25,12 +25,22 @@ AGENT = -1
 
 
 @pytest.mark.parametrize("res", [{"registers": 1}, {"registers": 0}, {"layout": 1}])
-def test_exec_steps_match_oracle(res):
-    n_books, cap, Wn, n_steps, F = 24, 100, 100, 16, 64
+@pytest.mark.parametrize("cap,reverse", [(100, False), (100, True), (300, True)])
+def test_exec_steps_match_oracle(res, cap, reverse):
+    """reverse: in every other book, every third window carries its time stamps in
+    reverse order, so that the book's times go backwards (Section 4.1 time priority):
+    capacity 100 runs the register kernel's timed loop, which writes the level-1 rows
+    too; capacity 300 hands such books to the LDS engine after the launch."""
+    n_books, Wn, n_steps, F = 24, 100, 16, 64
     w = W.uniform(n_books, Wn * n_steps, cap=cap, tag=13)
     seeds = 2 * (cap // 2)
-    msgs = w.msgs.reshape(n_books, seeds + Wn * n_steps, 8)
-    ctx = lob.Context(w.caps, l2_levels=10, trade_log_records=np.full(n_books, 2 * (Wn + 4) + 8))
+    msgs = w.msgs.reshape(n_books, seeds + Wn * n_steps, 8).copy()
+    if reverse:
+        for b in range(0, n_books, 2):
+            for k in range(b % 3, n_steps, 3):
+                blk = msgs[b, seeds + k * Wn:seeds + (k + 1) * Wn]
+                blk[:, 6:8] = blk[::-1, 6:8].copy()
+    ctx = lob.Context(w.caps, l2_levels=10, trade_log_records=np.full(n_books, 2 * (Wn + 4) + 2 * cap))
     ctx.set_plan(**res)
     ctx.process(to_dev(msgs[:, :seeds].reshape(-1, 8)), to_dev(np.arange(n_books + 1, dtype=np.int64) * seeds))
     rng = np.random.default_rng(3)
@@ -85,6 +95,8 @@ def test_exec_steps_match_oracle(res):
             np.testing.assert_array_equal(dump[i, sd, :len(want)], want)
     # the steps' trades left the log (keep_trades off)
     assert (ctx.read_status()["log_records"] == 0).all()
+    if reverse:
+        assert ((ctx.read_status()["flags"] & lob.BOOK_TIME_ORDER) != 0)[::2].all()
 
 
 
