@@ -908,13 +908,13 @@ __device__ __forceinline__ void write_l2(const Book &bk, const RState &st, int L
 // write_l2 with L = 1 (the per-message rows of the execution environment): each
 // side's best price and the exact quantity resting at it, min(sum, INT_MAX); an empty
 // side has quantity 0 and an unspecified price (the execution step tells the sides
-// apart by quantity).  A side
-// is sorted by price, so the best level is every slot holding slot 0's price; lane l
-// adds its two register slots (l and 64 + l) and one saturating scan per side sums
-// the lanes (saturating adds of non-negative values give min(sum, INT_MAX) in any
-// order), the two sides' scans independent of each other; when neither best price
-// has a second order, slot 0's quantities are the sums and the scans are skipped.
-// With a tail, a level that goes on past slot 127 takes the general form.
+// apart by quantity).  A side is sorted by price, so the best level is every slot
+// holding slot 0's price; lane l adds its two register slots (l and 64 + l) and one
+// saturating scan per side sums the lanes (saturating adds of non-negative values
+// give min(sum, INT_MAX) in any order), the two sides' scans independent of each
+// other; when neither best price has a second order, slot 0's quantities are the
+// sums and the scans are skipped.  With a tail, a level that goes on past slot 127
+// takes the general form.
 __device__ __forceinline__ int l1_lane_qty(const Side &S, int n, int p0) {
   const int l = lane_id();
   const int x = l < n && S.c0.p == p0 ? S.c0.q : 0;
