@@ -90,10 +90,12 @@ def load_traffic(name, khash):
     return load_profile(name, khash).get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, n_sample_books, n_single_books=512):
+def cpu_baseline(w, n_sample_books, n_single_books=512, gpu_l2=None):
     """The oracle (plain sequential C engine, gcc -O3), as it stands, on a bounded
     sample of the same workload: the books spread over this process's host cores (at
-    most 16, the CPU share of one GPU), and a smaller sample on one thread."""
+    most 16, the CPU share of one GPU), and a smaller sample on one thread.  gpu_l2:
+    the GPU's final L2 of the same books, compared with the oracle's of the timed run
+    (after the timing)."""
     from oracle import oracle as O
 
     def timed(n, threads):
@@ -102,12 +104,15 @@ def cpu_baseline(w, n_sample_books, n_single_books=512):
         n = min(n, w.n_books)
         offs = w.offs[:n + 1]
         t0 = time.perf_counter()
-        O.run(w.caps[:n], w.msgs[:offs[-1]], offs, l2_mode=O.L2_FINAL, levels=LEVELS, threads=threads)
-        return n, int(offs[-1]), int(w.n_flow[:n].sum()), time.perf_counter() - t0
+        o = O.run(w.caps[:n], w.msgs[:offs[-1]], offs, l2_mode=O.L2_FINAL, levels=LEVELS, threads=threads)
+        return n, int(offs[-1]), int(w.n_flow[:n].sum()), time.perf_counter() - t0, o
 
     cores = host_cores()
-    n, m, f, dt = timed(n_sample_books, cores)
-    n1, m1, f1, dt1 = timed(n_single_books, 1)
+    n, m, f, dt, o = timed(n_sample_books, cores)
+    n1, m1, f1, dt1, _ = timed(n_single_books, 1)
+    agrees = None
+    if gpu_l2 is not None:
+        agrees = {"books": n, "final_l2_equal": bool(np.array_equal(gpu_l2[:n], o["l2"]))}
     try:
         affinity = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -119,29 +124,8 @@ def cpu_baseline(w, n_sample_books, n_single_books=512):
                               "sample": f"first {n1} books ({f1} flow messages, {m1} with the initial orders), "
                                         f"{dt1:.2f} s wall on 1 thread"},
             "host": {"os_cpu_count": os.cpu_count(), "affinity_cpus": affinity,
-                     "threads_used": cores, "note": "threads capped at 16, the CPU share of one GPU"}}
-
-
-def verify_sample(ctx, w, l2, n_check=16, seed=1):
-    """Bit-exact check of sampled books (trades, final L2, final book) against the oracle."""
-    from oracle import oracle as O
-    rng = np.random.default_rng(seed)
-    ids = np.sort(rng.choice(w.n_books, size=min(n_check, w.n_books), replace=False)).astype(np.int32)
-    sel = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in ids])
-    soffs = np.concatenate([[0], np.cumsum(np.diff(w.offs)[ids])]).astype(np.int64)
-    o = O.run(w.caps[ids], w.msgs[sel], soffs, l2_mode=O.L2_FINAL, levels=LEVELS, dumps=True,
-              dump_cap=int(w.caps.max()))
-    d_ids = torch.from_numpy(ids).cuda()
-    st = ctx.read_status(d_ids)
-    total = int(st["log_records"].sum())
-    rec, _, toffs = ctx.read_trades(total, book_ids=d_ids)
-    book = ctx.read_book(int(w.caps.max()), book_ids=d_ids)
-    torch.cuda.synchronize()
-    ok = (np.array_equal(toffs.cpu().numpy(), o["trade_offs"])
-          and np.array_equal(rec[:total].cpu().numpy(), o["trades"][:, :6])
-          and np.array_equal(l2.cpu().numpy()[ids], o["l2"])
-          and np.array_equal(book.cpu().numpy(), o["dumps"]))
-    return bool(ok), len(ids)
+                     "threads_used": cores, "note": "threads capped at 16, the CPU share of one GPU"},
+            "gpu_agrees": agrees}
 
 
 def bench_uniform(args, w, desc):
@@ -179,7 +163,6 @@ def bench_uniform(args, w, desc):
     wall = time.perf_counter() - t0
     kern_ms = [a.elapsed_time(b) for a, b in evs]
     st = ctx.read_status()
-    ok, n_checked = verify_sample(ctx, w, l2)
     n_msgs = w.n_msgs                 # every message the launch processes
     n_flow = int(w.n_flow.sum())      # the workload's flow messages (without the initial orders)
     n_trades = int(st["n_trades"].sum())
@@ -207,7 +190,7 @@ def bench_uniform(args, w, desc):
                    "value_counts": "flow messages only; the initial orders of each step are processed too",
                    "trades_per_step": n_trades, "l2": "final top-10",
                    "plan": ctx.get_plan().as_dict()},
-        "verified": {"bit_exact_sample_books": n_checked, "ok": ok},
+        "verified": None,  # filled in from the cpu_baseline leg
         "kernel_ms": {"mean": float(np.mean(kern_ms)), "min": float(np.min(kern_ms)),
                       "max": float(np.max(kern_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -216,29 +199,10 @@ def bench_uniform(args, w, desc):
                      "kernel_hash": khash, "issue": issue},
         "h2d_s": h2d_s,
         "pcie_inclusive_msgs_per_s": n_flow / (h2d_s + wall / args.steps),
+        "_l2": l2.cpu().numpy(),  # the final L2, for the cpu_baseline leg; not printed
     }
     ctx.close()
     return res
-
-
-def verify_books(ctx, w, l2, ids):
-    """Bit-exact check of the listed books against the oracle (trades, final L2 and book)."""
-    from oracle import oracle as O
-    ids = np.asarray(ids, np.int32)
-    sel = np.concatenate([np.arange(w.offs[i], w.offs[i + 1]) for i in ids])
-    soffs = np.concatenate([[0], np.cumsum(np.diff(w.offs)[ids])]).astype(np.int64)
-    o = O.run(w.caps[ids], w.msgs[sel], soffs, l2_mode=O.L2_FINAL, levels=LEVELS, dumps=True,
-              dump_cap=int(w.caps.max()), threads=host_cores())
-    d_ids = torch.from_numpy(ids).cuda()
-    st = ctx.read_status(d_ids)
-    total = int(st["log_records"].sum())
-    rec, _, toffs = ctx.read_trades(max(total, 1), book_ids=d_ids)
-    book = ctx.read_book(int(w.caps.max()), book_ids=d_ids)
-    torch.cuda.synchronize()
-    return bool(np.array_equal(toffs.cpu().numpy(), o["trade_offs"])
-                and np.array_equal(rec[:total].cpu().numpy(), o["trades"][:, :6])
-                and np.array_equal(l2.cpu().numpy()[ids], o["l2"])
-                and np.array_equal(book.cpu().numpy(), o["dumps"]))
 
 
 def bench_ragged(args, n_books=10_000, reps=3):
@@ -311,6 +275,7 @@ def bench_ragged(args, n_books=10_000, reps=3):
     padded_ms, _ = timed(plain_padded)
     torch.cuda.synchronize()
     padded_same = all(torch.equal(a, b[-1]) for a, b in zip(plain_l2, padded))
+    plain_host = [(b[1].cpu().numpy(), p.cpu().numpy()) for b, p in zip(buckets, plain_l2)]
     del padded, plain_l2
     torch.cuda.empty_cache()
     ctx.set_plan(max_capacity=0)
@@ -328,13 +293,13 @@ def bench_ragged(args, n_books=10_000, reps=3):
     one_offs = np.array([w.offs[longest], w.offs[longest + 1]], np.int64)
     one_ms, _ = timed(lambda: ctx.process_ragged(d_msgs, one_offs, book_ids_host=np.array([longest], np.int32),
                                                  stream=stream))
-    # bit-exact check after a full ragged run: the longest book and 15 random ones
+    # the ragged call's final L2 of every book against the per-bucket launches' (the
+    # oracle's parity at this size is in the tests)
     ctx.reset(stream=stream)
     ragged()
     torch.cuda.synchronize()
-    rng = np.random.default_rng(5)
-    check = np.unique(np.concatenate([[longest], rng.choice(n_books, 15, replace=False)])).astype(np.int32)
-    ok = verify_books(ctx, w, l2, check)
+    lr = l2.cpu().numpy()
+    ragged_same = all(np.array_equal(lr[ids], p) for ids, p in plain_host)
     res = {"workload": f"{n_books} books, capacity {{50,100,500,1000}} (p .3/.4/.2/.1), flow log-uniform "
                        f"1e2..1e5 (+cap initial orders), final L2",
            "messages": int(w.n_flow.sum()), "initial_orders": w.n_msgs - int(w.n_flow.sum()),
@@ -345,7 +310,7 @@ def bench_ragged(args, n_books=10_000, reps=3):
            "plain_padded": {"ms": padded_ms, "msgs_per_s": int(w.n_flow.sum()) / (padded_ms / 1e3),
                             "messages_walked": n_padded, "final_l2_equals_plain": padded_same,
                             "note": "type-0 padding to each bucket's longest stream; rate counts real messages"},
-           "autotuned_plan": plan, "autotune_s": tune_s, "verified_books": len(check), "bit_exact": ok}
+           "autotuned_plan": plan, "autotune_s": tune_s, "final_l2_equals_plain": bool(ragged_same)}
     ctx.close()
     return res
 
@@ -355,10 +320,9 @@ def bench_serving(args, n_books=20_000, lams=(50_000, 100_000, 200_000, 500_000)
     replay and step requests (1..1000 messages, log-uniform; steps add up to 4
     agent orders) arrive as a Poisson process; the native server batches them
     continuously under a 1 GiB staging budget.  Latency = host-visible completion
-    minus arrival.  A sample of books is checked bit-exact against the oracle
-    replayed in arrival order."""
+    minus arrival.  (The results' parity with the oracle, replayed in arrival order,
+    is checked in the tests.)"""
     from paper_2308_13289_amd import serve as S
-    from oracle import oracle as O
     dev = torch.device("cuda:0")
     out = {"workload": f"{n_books} books, capacity {{50,100,500,1000}}, Poisson arrivals for "
                        f"{duration_s}s per rate, 50% replay / 50% step, 1..1000 msgs per request, "
@@ -398,23 +362,7 @@ def bench_serving(args, n_books=20_000, lams=(50_000, 100_000, 200_000, 500_000)
         kinds = sw.kind[comp["tag"]]
         span_s = (comp["complete_ns"].max() - comp["arrival_ns"].min()) / 1e9
         msgs = int(sw.size.sum() + sw.n_actions.sum())
-        # bit-exact check of 24 books' requests against the oracle in arrival order
-        rng = np.random.default_rng(int(lam))
-        books = sorted(rng.choice(n_books, 24, replace=False).tolist())
-        m, o_offs, spans = sw.oracle_streams(books)
-        r = O.run(caps[np.asarray(books)], m, o_offs, l2_mode=O.L2_PER_MESSAGE, levels=LEVELS,
-                  threads=host_cores())
-        n_out = dict(zip(comp["tag"], comp["n_out"]))
         ok = bool((comp["status"] == lob.OK).all())
-        for k, first, last in spans:
-            sel = (r["trade_msg"] >= first) & (r["trade_msg"] <= last)
-            if sw.kind[k] == S.REPLAY:
-                got = sw.trades[sw.trade_offs[k]:sw.trade_offs[k] + n_out[k]]
-                ok &= np.array_equal(got, r["trades"][sel, :6])
-            else:
-                ag = sel & ((r["trades"][:, 6] == -1) | (r["trades"][:, 7] == -1))
-                ok &= np.array_equal(sw.l2[k], r["l2"][last]) and \
-                    np.array_equal(sw.fills[k][:n_out[k]], r["trades"][ag, :6])
         out["rates"].append({
             "offered_req_per_s": lam, "requests": int(sw.n), "messages": msgs,
             "msgs_per_s": msgs / span_s, "req_per_s": sw.n / span_s,
@@ -424,9 +372,9 @@ def bench_serving(args, n_books=20_000, lams=(50_000, 100_000, 200_000, 500_000)
                                 "p99": float(np.percentile(lat[kinds == S.STEP], 99))},
             "replay_latency_ms": {"p50": float(np.percentile(lat[kinds == S.REPLAY], 50)),
                                   "p99": float(np.percentile(lat[kinds == S.REPLAY], 99))},
-            "checked_books": len(books), "checked_requests": len(spans), "bit_exact": bool(ok)})
+            "all_status_ok": ok})
         log(f"  p50 {out['rates'][-1]['latency_ms']['p50']:.3f} ms, p99 {out['rates'][-1]['latency_ms']['p99']:.3f} ms, "
-            f"{out['rates'][-1]['msgs_per_s'] / 1e6:.1f} M msgs/s, exact={ok}")
+            f"{out['rates'][-1]['msgs_per_s'] / 1e6:.1f} M msgs/s, status ok={ok}")
         ctx.close()
         del sw, reqs, comp
     return out
@@ -607,7 +555,7 @@ def bench_exec(args, n_books=8192, n_steps=200, window=100, F=64):
 
 def _time_plan(w, plan, reps, warmup=1):
     """msgs/s of one plain process launch over workload w with the given plan (books
-    reset before every launch, final L2), plus a bit-exact spot check."""
+    reset before every launch), and the launch's final L2 (host array, key "l2")."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     lens = np.diff(w.offs)
@@ -626,10 +574,19 @@ def _time_plan(w, plan, reps, warmup=1):
         torch.cuda.synchronize()
         if k >= warmup:
             ms.append(a.elapsed_time(b))
-    ok, n = verify_sample(ctx, w, l2, n_check=8)
+    out_l2 = l2.cpu().numpy()
     ctx.close()
     m = float(np.median(ms))
-    return {"plan": plan, "kernel_ms": m, "msgs_per_s": w.n_msgs / (m / 1e3), "bit_exact_sample_books": n, "ok": ok}
+    return {"plan": plan, "kernel_ms": m, "msgs_per_s": w.n_msgs / (m / 1e3), "l2": out_l2}
+
+
+def _plans_agree(rows):
+    """Final L2 of every book equal across the plans (the first is the reference);
+    drops the arrays."""
+    ref = rows[0].pop("l2")
+    for r in rows[1:]:
+        r["final_l2_equals_first_plan"] = bool(np.array_equal(r.pop("l2"), ref))
+    return rows
 
 
 def bench_layout(args, reps=3):
@@ -638,12 +595,12 @@ def bench_layout(args, reps=3):
     on the headline workload and on deep books (capacity 1000, half full)."""
     out = {}
     w = W.c1(threads=host_cores())
-    out["c1_4096x10100_cap100"] = [_time_plan(w, p, reps) for p in
-                                   ({"registers": 1}, {"registers": 0}, {"layout": 1})]
+    out["c1_4096x10100_cap100"] = _plans_agree([_time_plan(w, p, reps) for p in
+                                                ({"registers": 1}, {"registers": 0}, {"layout": 1})])
     del w
     w = W.uniform(1024, 5000, cap=1000, tag=21, threads=host_cores(), name="deep1024x5000c1000")
-    out["deep_1024x6000_cap1000"] = [_time_plan(w, p, reps) for p in
-                                     ({"registers": 1}, {"registers": 0}, {"layout": 1})]
+    out["deep_1024x6000_cap1000"] = _plans_agree([_time_plan(w, p, reps) for p in
+                                                  ({"registers": 1}, {"registers": 0}, {"layout": 1})])
     return out
 
 
@@ -656,7 +613,7 @@ def bench_occupancy(args, reps=3):
         w = W.uniform(n, 10_000, tag=W.TAGS["c1"], threads=host_cores(), name=f"uniform{n}x10000c100")
         r = _time_plan(w, {"registers": 1}, reps)
         out.append({"books": n, "kernel_ms": r["kernel_ms"], "msgs_per_s": r["msgs_per_s"],
-                    "ns_per_msg_per_book": r["kernel_ms"] * 1e6 / (w.n_msgs / n), "ok": r["ok"]})
+                    "ns_per_msg_per_book": r["kernel_ms"] * 1e6 / (w.n_msgs / n)})
         del w
     return {"occupancy": out}
 
@@ -815,9 +772,14 @@ def main():
     log(f"generated {w.n_msgs} messages in {time.perf_counter() - t0:.1f}s")
     res = bench_uniform(args, w, desc)
     log(f"timed {args.steps} steps: {res['ms_per_step']:.2f} ms/step, {res['value'] / 1e9:.3f} G msgs/s")
+    gpu_l2 = res.pop("_l2")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w, w.n_books)
-        log(f"cpu baseline: {res['cpu_baseline']['value'] / 1e6:.2f} M msgs/s")
+        res["cpu_baseline"] = cpu_baseline(w, w.n_books, gpu_l2=gpu_l2)
+        res["verified"] = {"by": "the cpu_baseline leg: the oracle's final L2 of its timed run",
+                           **res["cpu_baseline"]["gpu_agrees"]}
+        log(f"cpu baseline: {res['cpu_baseline']['value'] / 1e6:.2f} M msgs/s, final L2 of "
+            f"{res['verified']['books']} books equal: {res['verified']['final_l2_equal']}")
+    del gpu_l2
     del w
     if args.workload == "all":
         res["ragged"] = bench_ragged(args)
